@@ -1,0 +1,112 @@
+"""Algorithm 1 (Section 3) end to end, with the exact least-squares product.
+
+Outputs follow the problem statement of Section 1 and the output line of
+Algorithm 1: permutations P (rows) and Q (columns), L (m x l, unit lower
+trapezoidal) and U (l x n, upper trapezoidal) with P A Q ~ L U.
+
+Permutations are index vectors: (PA)[i, :] = A[perm_r[i], :] and
+(AQ)[:, j] = A[:, perm_c[j]].
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import rng, lu, lstsq
+from . import sketch as sk
+
+
+@dataclass
+class Params:
+    k: int
+    l: int
+    s: int
+    seed: int
+
+
+@dataclass
+class Result:
+    L: np.ndarray
+    U: np.ndarray
+    perm_r: np.ndarray
+    perm_c: np.ndarray
+    ipiv_r: np.ndarray
+    ipiv_c: np.ndarray
+    Y: np.ndarray
+    Ly: np.ndarray
+    Uy: np.ndarray
+    B: np.ndarray
+    Lt: np.ndarray
+    zero_pivots_y: int = 0
+    zero_pivots_b: int = 0
+    min_gap_y: float = np.inf
+    min_gap_b: float = np.inf
+    extra: dict = field(default_factory=dict)
+
+
+def check_params(m: int, n: int, p: Params):
+    """Validity of one projection: 1 <= k <= l <= min(m, n), l <= s, s = 2^b."""
+    if m < 1 or n < 1:
+        raise ValueError("empty matrix")
+    if not (1 <= p.k <= p.l <= min(m, n)):
+        raise ValueError("need 1 <= k <= l <= min(m, n)")
+    if p.s < 2 or p.s & (p.s - 1) or p.s > 65536:
+        raise ValueError("s must be a power of two in [2, 65536]")
+    if p.l > p.s:
+        raise ValueError("need l <= s")
+
+
+def sketch_params(n: int, p: Params):
+    h, sgn = rng.sem_hash(p.seed, n, p.s)
+    d = rng.srft_signs(p.seed, p.s)
+    sel = rng.srft_select(p.seed, p.s, p.l)
+    return h, sgn, d, sel
+
+
+def sketch_y(A, p: Params, csr=None):
+    """Algorithm 1 steps 1-2: Y = A Omega_1^T."""
+    if csr is not None:
+        row_ptr, col, val, m, n = csr
+        check_params(m, n, p)
+        h, sgn, d, sel = sketch_params(n, p)
+        return sk.sketch_csr(row_ptr, col, val, m, n, h, sgn, d, sel, p.s)
+    A = np.asarray(A, dtype=np.float64)
+    check_params(*A.shape, p)
+    h, sgn, d, sel = sketch_params(A.shape[1], p)
+    return sk.sketch_dense(A, h, sgn, d, sel, p.s)
+
+
+def rlu(A, p: Params, csr=None) -> Result:
+    """Algorithm 1 with B = L_y^+ P A exactly (Corollary 3.2's product).
+
+    ``A`` is a dense array, or None with ``csr = (row_ptr, col, val, m, n)``.
+    """
+    if csr is not None:
+        row_ptr, col, val, m, n = csr
+        Aop = sp.csr_matrix((np.asarray(val, dtype=np.float64), np.asarray(col),
+                             np.asarray(row_ptr)), shape=(m, n))
+    else:
+        Aop = np.asarray(A, dtype=np.float64)
+    Y = sketch_y(Aop if csr is None else None, p, csr=csr)          # steps 1-2
+    Ly, Uy, perm_r, ipiv_r, zy, gy = lu.gepp(Y)                   # step 3
+    Lhat = lstsq.unpermute_rows(Ly, perm_r)
+    B = lstsq.lstsq_product(Lhat, Aop)                            # steps 5-6 (exact)
+    Lt, U, perm_c, ipiv_c, zb, gb = lu.colpiv_lu(B)               # step 6
+    L = Ly @ Lt                                                   # step 7
+    return Result(L=L, U=U, perm_r=perm_r, perm_c=perm_c, ipiv_r=ipiv_r,
+                  ipiv_c=ipiv_c, Y=Y, Ly=Ly, Uy=Uy, B=B, Lt=Lt,
+                  zero_pivots_y=zy, zero_pivots_b=zb, min_gap_y=gy, min_gap_b=gb)
+
+
+def residual_fro(A, L, U, perm_r, perm_c) -> float:
+    """||L U - P A Q||_F for dense A."""
+    A = np.asarray(A, dtype=np.float64)
+    return float(np.linalg.norm(L @ U - A[np.ix_(perm_r, perm_c)]))
+
+
+def tail_norm(A, k: int) -> float:
+    """Delta_k(A) = sqrt(sum_{i > k} sigma_i^2) (Section 1), by full SVD."""
+    sv = np.linalg.svd(np.asarray(A, dtype=np.float64), compute_uv=False)
+    return float(np.sqrt(np.sum(sv[k:] ** 2)))
