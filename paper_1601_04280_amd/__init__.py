@@ -1,0 +1,317 @@
+"""Python binding of librlu: the MI355X sparse-projection randomized LU.
+
+Argument marshalling only.  Every step of the decomposition runs in the HIP
+library (``csrc/``, built into ``librlu.so``); torch provides device memory
+(tensors' ``data_ptr()``) and the current HIP stream.  There is no CPU
+fallback: without the built library every call raises.
+
+Method: Aizenbud, Shabat & Averbuch, "Randomized LU decomposition using
+sparse projections" (arXiv 1601.04280), Algorithm 1, with the exact
+least-squares product of Corollary 3.2.  See ``include/rlu.h`` for the
+conventions (pivot ties, zero pivots, parameter generator, real transform).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+__all__ = [
+    "RluError", "Context", "Factorization", "sketch_params", "sketch", "factor", "tall_lu",
+    "library_path", "load_library", "PRECISIONS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "librlu.so")
+
+RLU_OK, RLU_ERR_INVALID_ARG, RLU_ERR_NO_MEMORY, RLU_ERR_DEVICE, RLU_ERR_NUMERIC, RLU_ERR_AGAIN, \
+    RLU_ERR_UNKNOWN_TICKET = range(7)
+STATUS_NAMES = {0: "RLU_OK", 1: "RLU_ERR_INVALID_ARG", 2: "RLU_ERR_NO_MEMORY", 3: "RLU_ERR_DEVICE",
+                4: "RLU_ERR_NUMERIC", 5: "RLU_ERR_AGAIN", 6: "RLU_ERR_UNKNOWN_TICKET"}
+RLU_DENSE_ROW_MAJOR, RLU_CSR = 0, 1
+RLU_F64, RLU_F32 = 0, 1
+PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2}
+RLU_FLAG_VALIDATE = 1
+RLU_FLAG_TIMING = 2
+STAGES = ["params", "sketch", "lu_y", "contract", "gram", "chol", "solve", "lu_b", "assemble"]
+
+
+class RluError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Matrix(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("layout", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("values", ctypes.c_void_p), ("ld", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p), ("nnz", ctypes.c_int64)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("l", ctypes.c_int32), ("s", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("zero_pivots_y", ctypes.c_int32),
+                ("zero_pivots_b", ctypes.c_int32), ("nonfinite", ctypes.c_int32),
+                ("timeouts", ctypes.c_int32), ("bad_index", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+class Factors(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_void_p), ("ldl", ctypes.c_int64), ("U", ctypes.c_void_p),
+                ("ldu", ctypes.c_int64), ("perm_r", ctypes.c_void_p), ("perm_c", ctypes.c_void_p),
+                ("ipiv_r", ctypes.c_void_p), ("ipiv_c", ctypes.c_void_p), ("Y", ctypes.c_void_p),
+                ("ldy", ctypes.c_int64), ("Uy", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("info", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load librlu.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(library_path):
+        raise RuntimeError(f"{library_path} is missing: build it with __graft_entry__.build() "
+                           "(python paper_1601_04280_amd/build.py)")
+    lib = ctypes.CDLL(library_path)
+    P, I64, I32, U64, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t
+    sig = {
+        "rlu_create": (I32, [I32, ctypes.POINTER(P)]),
+        "rlu_destroy": (I32, [P]),
+        "rlu_workspace_size": (I32, [P, ctypes.POINTER(Matrix), ctypes.POINTER(Params), ctypes.POINTER(SZ)]),
+        "rlu_sketch_params": (I32, [ctypes.POINTER(Params), I64, P, P, P, P, P]),
+        "rlu_sketch": (I32, [P, ctypes.POINTER(Matrix), ctypes.POINTER(Params), P, I64, P, SZ, P]),
+        "rlu_factor": (I32, [P, ctypes.POINTER(Matrix), ctypes.POINTER(Params), ctypes.POINTER(Factors),
+                              P, SZ, P]),
+        "rlu_tall_lu": (I32, [P, P, I64, I64, I64, P, P, P, P, P, P, SZ, P]),
+        "rlu_tall_lu_workspace_size": (I32, [P, I64, I64, ctypes.POINTER(SZ)]),
+        "rlu_serve_start": (I32, [P, SZ, I32]),
+        "rlu_submit": (I32, [P, ctypes.POINTER(Matrix), ctypes.POINTER(Params), ctypes.POINTER(Factors),
+                              ctypes.POINTER(U64)]),
+        "rlu_poll": (I32, [P, U64]),
+        "rlu_serve_stop": (I32, [P]),
+        "rlu_stage_times": (I32, [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(I32)]),
+        "rlu_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != RLU_OK:
+        msg = load_library().rlu_last_error().decode(errors="replace")
+        raise RluError(status, msg)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(device) -> int:
+    torch = _torch()
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Context:
+    """One rlu_ctx on a device, plus a cached workspace tensor."""
+
+    def __init__(self, device: int = 0):
+        lib = load_library()
+        self.device = device
+        self._h = ctypes.c_void_p()
+        _check(lib.rlu_create(device, ctypes.byref(self._h)))
+        self._ws = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace(self, nbytes: int):
+        torch = _torch()
+        nbytes = max(256, int(nbytes))
+        if self._ws is None or self._ws.numel() < nbytes + 256:
+            self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=f"cuda:{self.device}")
+        base = self._ws.data_ptr()
+        off = (-base) % 256
+        return base + off, self._ws.numel() - off
+
+    def stage_times(self):
+        """{stage: total ms} over calls made with RLU_FLAG_TIMING since the last read, and the call count."""
+        ms = (ctypes.c_float * len(STAGES))()
+        calls = ctypes.c_int(0)
+        _check(load_library().rlu_stage_times(self._h, ms, ctypes.byref(calls)))
+        return {name: float(ms[i]) for i, name in enumerate(STAGES)}, calls.value
+
+    def close(self):
+        if self._h:
+            load_library().rlu_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+def _params(k, l, s, seed, precision="f64", flags=0) -> Params:
+    return Params(int(k), int(l), int(s), PRECISIONS[precision], int(seed) & ((1 << 64) - 1),
+                  int(flags), 0)
+
+
+def _dense_matrix(A) -> Matrix:
+    torch = _torch()
+    if A.dim() != 2 or not A.is_cuda:
+        raise ValueError("A must be a 2-D CUDA (HIP) tensor")
+    if A.stride(1) != 1:
+        raise ValueError("A must be row major (stride(1) == 1)")
+    if A.dtype == torch.float64:
+        dt = RLU_F64
+    elif A.dtype == torch.float32:
+        dt = RLU_F32
+    else:
+        raise ValueError("A must be float64 or float32")
+    return Matrix(A.shape[0], A.shape[1], RLU_DENSE_ROW_MAJOR, dt, A.data_ptr(), A.stride(0), None, None, 0)
+
+
+def _csr_matrix(row_ptr, col, val, m, n) -> Matrix:
+    torch = _torch()
+    for t, dt in ((row_ptr, torch.int32), (col, torch.int32), (val, torch.float64)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise ValueError("CSR arrays must be contiguous CUDA tensors (int32, int32, float64)")
+    return Matrix(int(m), int(n), RLU_CSR, RLU_F64, val.data_ptr(), 0, row_ptr.data_ptr(),
+                  col.data_ptr(), int(val.numel()))
+
+
+def sketch_params(n: int, l: int, s: int, seed: int, device: int = 0):
+    """Device-drawn (h, sgn, d, sel) exactly as the compute calls draw them."""
+    torch = _torch()
+    dev = f"cuda:{device}"
+    h = torch.empty(n, dtype=torch.int32, device=dev)
+    sgn = torch.empty(n, dtype=torch.int8, device=dev)
+    d = torch.empty(s, dtype=torch.int8, device=dev)
+    sel = torch.empty(l, dtype=torch.int32, device=dev)
+    p = _params(1, l, s, seed)
+    _check(load_library().rlu_sketch_params(ctypes.byref(p), n, h.data_ptr(), sgn.data_ptr(),
+                                            d.data_ptr(), sel.data_ptr(), _stream(device)))
+    return h, sgn, d, sel
+
+
+def sketch(A=None, *, k: int, l: int, s: int, seed: int, csr=None, ctx: Context = None, Y=None):
+    """Algorithm 1 steps 1-2: Y = A Omega_1^T on the device (m x l, float64)."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    mat = _dense_matrix(A) if csr is None else _csr_matrix(*csr)
+    p = _params(k, l, s, seed)
+    lib = load_library()
+    nbytes = ctypes.c_size_t()
+    _check(lib.rlu_workspace_size(ctx.handle, ctypes.byref(mat), ctypes.byref(p), ctypes.byref(nbytes)))
+    ws, wsb = ctx.workspace(nbytes.value)
+    if Y is None:
+        Y = torch.empty(mat.m, l, dtype=torch.float64, device=f"cuda:{ctx.device}")
+    _check(lib.rlu_sketch(ctx.handle, ctypes.byref(mat), ctypes.byref(p), Y.data_ptr(), Y.stride(0), ws,
+                          wsb, _stream(ctx.device)))
+    return Y
+
+
+@dataclass
+class Factorization:
+    L: object
+    U: object
+    perm_r: object
+    perm_c: object
+    ipiv_r: object
+    ipiv_c: object
+    Y: object
+    Uy: object
+    B: object
+    info: object          # device int32[8] (rlu_info)
+
+    def info_dict(self):
+        v = self.info.cpu().tolist()
+        return {"status": v[0], "zero_pivots_y": v[1], "zero_pivots_b": v[2], "nonfinite": v[3],
+                "timeouts": v[4], "bad_index": v[5]}
+
+
+def factor(A=None, *, k: int, l: int, s: int, seed: int, precision: str = "f64", csr=None,
+           ctx: Context = None, keep_intermediates: bool = False, check: bool = True, flags: int = 0,
+           out: Factorization = None) -> Factorization:
+    """PAQ ~ LU on the device.  ``check`` synchronises and raises on a device-side error."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    mat = _dense_matrix(A) if csr is None else _csr_matrix(*csr)
+    m, n = mat.m, mat.n
+    p = _params(k, l, s, seed, precision, flags)
+    lib = load_library()
+    nbytes = ctypes.c_size_t()
+    _check(lib.rlu_workspace_size(ctx.handle, ctypes.byref(mat), ctypes.byref(p), ctypes.byref(nbytes)))
+    ws, wsb = ctx.workspace(nbytes.value)
+    dev = f"cuda:{ctx.device}"
+    if out is None:
+        f64, i32 = torch.float64, torch.int32
+        out = Factorization(
+            L=torch.empty(m, l, dtype=f64, device=dev), U=torch.empty(l, n, dtype=f64, device=dev),
+            perm_r=torch.empty(m, dtype=i32, device=dev), perm_c=torch.empty(n, dtype=i32, device=dev),
+            ipiv_r=torch.empty(l, dtype=i32, device=dev), ipiv_c=torch.empty(l, dtype=i32, device=dev),
+            Y=torch.empty(m, l, dtype=f64, device=dev) if keep_intermediates else None,
+            Uy=torch.empty(l, l, dtype=f64, device=dev) if keep_intermediates else None,
+            B=torch.empty(l, n, dtype=f64, device=dev) if keep_intermediates else None,
+            info=torch.zeros(8, dtype=i32, device=dev))
+    f = Factors(out.L.data_ptr(), out.L.stride(0), out.U.data_ptr(), out.U.stride(0), out.perm_r.data_ptr(),
+                out.perm_c.data_ptr(), _ptr(out.ipiv_r), _ptr(out.ipiv_c), _ptr(out.Y),
+                out.Y.stride(0) if out.Y is not None else 0, _ptr(out.Uy), _ptr(out.B), out.info.data_ptr())
+    _check(lib.rlu_factor(ctx.handle, ctypes.byref(mat), ctypes.byref(p), ctypes.byref(f), ws, wsb,
+                          _stream(ctx.device)))
+    if check:
+        st = int(out.info[0].item())
+        if st != RLU_OK:
+            raise RluError(st, f"device-side failure, info={out.info_dict()}")
+    return out
+
+
+def tall_lu(X, ctx: Context = None, check: bool = True):
+    """Row-pivoted LU of a tall float64 device matrix: returns (Lhat, U, perm, ipiv, info)."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    rows, cols = X.shape
+    lib = load_library()
+    nbytes = ctypes.c_size_t()
+    _check(lib.rlu_tall_lu_workspace_size(ctx.handle, rows, cols, ctypes.byref(nbytes)))
+    ws, wsb = ctx.workspace(nbytes.value)
+    dev = X.device
+    Lhat = torch.empty(rows, cols, dtype=torch.float64, device=dev)
+    U = torch.empty(cols, cols, dtype=torch.float64, device=dev)
+    perm = torch.empty(rows, dtype=torch.int32, device=dev)
+    ipiv = torch.empty(cols, dtype=torch.int32, device=dev)
+    info = torch.zeros(8, dtype=torch.int32, device=dev)
+    _check(lib.rlu_tall_lu(ctx.handle, X.data_ptr(), rows, cols, X.stride(0), Lhat.data_ptr(), U.data_ptr(),
+                           perm.data_ptr(), ipiv.data_ptr(), info.data_ptr(), ws, wsb, _stream(ctx.device)))
+    if check and int(info[0].item()) != RLU_OK:
+        raise RluError(int(info[0].item()), f"device-side failure, info={info.tolist()}")
+    return Lhat, U, perm, ipiv, info

@@ -1,0 +1,512 @@
+// C ABI of the library: contexts, argument validation, workspace planning
+// and the stage sequence of Algorithm 1 (see include/rlu.h).
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "rlu_device.h"
+#include "rlu_internal.h"
+
+namespace rlu {
+
+static thread_local std::string g_last_error;
+
+rlu_status fail(rlu_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+rlu_status hip_fail(hipError_t e, const char *what) {
+  return fail(RLU_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void sketch_dense_set_attrs();
+int gepp_max_blocks_per_cu(size_t lds);
+
+constexpr int kMaxL = 576;  // l x 33 doubles of the Cholesky panel must fit in LDS
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+static bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+rlu_status validate_matrix(const rlu_matrix *A) {
+  if (!A) return fail(RLU_ERR_INVALID_ARG, "A is NULL");
+  if (A->m < 1 || A->n < 1) return fail(RLU_ERR_INVALID_ARG, "m and n must be >= 1 (m=%lld n=%lld)", (long long)A->m, (long long)A->n);
+  if (A->m > INT32_MAX || A->n > INT32_MAX) return fail(RLU_ERR_INVALID_ARG, "m and n must fit int32 indices");
+  if (!A->values && !(A->layout == RLU_CSR && A->nnz == 0)) return fail(RLU_ERR_INVALID_ARG, "A->values is NULL");
+  if (A->layout == RLU_DENSE_ROW_MAJOR) {
+    if (A->dtype != RLU_F64 && A->dtype != RLU_F32) return fail(RLU_ERR_INVALID_ARG, "dense dtype must be RLU_F64 or RLU_F32");
+    if (A->ld < A->n) return fail(RLU_ERR_INVALID_ARG, "ld (%lld) < n (%lld)", (long long)A->ld, (long long)A->n);
+  } else if (A->layout == RLU_CSR) {
+    if (A->dtype != RLU_F64) return fail(RLU_ERR_INVALID_ARG, "CSR values must be RLU_F64");
+    if (!A->row_ptr) return fail(RLU_ERR_INVALID_ARG, "CSR row_ptr is NULL");
+    if (!A->col_idx && A->nnz > 0) return fail(RLU_ERR_INVALID_ARG, "CSR col_idx is NULL");
+    if (A->nnz < 0 || A->nnz > INT32_MAX) return fail(RLU_ERR_INVALID_ARG, "CSR nnz out of range");
+  } else {
+    return fail(RLU_ERR_INVALID_ARG, "unknown layout %d", A->layout);
+  }
+  return RLU_OK;
+}
+
+rlu_status validate_params(const rlu_matrix *A, const rlu_params *p) {
+  if (!p) return fail(RLU_ERR_INVALID_ARG, "params is NULL");
+  if (p->reserved != 0) return fail(RLU_ERR_INVALID_ARG, "params.reserved must be 0");
+  if (p->s < 2 || p->s > kMaxS || !is_pow2(p->s)) return fail(RLU_ERR_INVALID_ARG, "s (%d) must be a power of two in [2, %d]", p->s, kMaxS);
+  if (p->l < 1 || p->l > p->s) return fail(RLU_ERR_INVALID_ARG, "need 1 <= l <= s (l=%d s=%d)", p->l, p->s);
+  if (p->k < 1 || p->k > p->l) return fail(RLU_ERR_INVALID_ARG, "need 1 <= k <= l (k=%d l=%d)", p->k, p->l);
+  if (A) {
+    if (p->l > A->m || p->l > A->n) return fail(RLU_ERR_INVALID_ARG, "need l <= min(m, n) (l=%d m=%lld n=%lld)", p->l, (long long)A->m, (long long)A->n);
+  }
+  if (p->l > kMaxL) return fail(RLU_ERR_INVALID_ARG, "l (%d) exceeds the supported maximum %d", p->l, kMaxL);
+  if (p->precision < RLU_PREC_F64 || p->precision > RLU_PREC_BF16_REFINED) return fail(RLU_ERR_INVALID_ARG, "unknown precision %d", p->precision);
+  if (p->flags & ~(RLU_FLAG_VALIDATE | RLU_FLAG_TIMING)) return fail(RLU_ERR_INVALID_ARG, "unknown flag bits 0x%x", p->flags);
+  return RLU_OK;
+}
+
+rlu_status validate_factors(const rlu_matrix *A, const rlu_params *p, const rlu_factors *out) {
+  if (!out) return fail(RLU_ERR_INVALID_ARG, "factors is NULL");
+  if (!out->L || !out->U || !out->perm_r || !out->perm_c) return fail(RLU_ERR_INVALID_ARG, "L, U, perm_r and perm_c are required");
+  if (!out->info) return fail(RLU_ERR_INVALID_ARG, "info (device record) is required");
+  if (out->ldl < p->l) return fail(RLU_ERR_INVALID_ARG, "ldl (%lld) < l (%d)", (long long)out->ldl, p->l);
+  if (out->ldu < A->n) return fail(RLU_ERR_INVALID_ARG, "ldu (%lld) < n (%lld)", (long long)out->ldu, (long long)A->n);
+  if (out->Y && out->ldy < p->l) return fail(RLU_ERR_INVALID_ARG, "ldy (%lld) < l (%d)", (long long)out->ldy, p->l);
+  if ((reinterpret_cast<uintptr_t>(out->info) & 3)) return fail(RLU_ERR_INVALID_ARG, "info must be 4-byte aligned");
+  return RLU_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace plan
+// ---------------------------------------------------------------------------
+struct Carver {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  }
+};
+
+struct FactorPlan {
+  int64_t m, n;
+  int l, s;
+  GeppPlan py, pb;
+  int splits_w, splits_g;
+  // offsets (bytes) into the workspace
+  size_t ctl, code, sel, twf, twp, Y, Wk, slots, Lhat, Uy, Wt, parts, Gm, Linv, Ginv, Bt, Lph,
+      Up, Lt, prec;
+  size_t total;
+  size_t sketch_total;
+};
+
+// control words: [0] barrier counter (Y), [1] abort flag, [2] barrier counter (B^T), [3] spare
+constexpr int kCtlWords = 64;
+
+static void plan_sketch_part(Carver &cv, FactorPlan &fp, int64_t n, int l, int s) {
+  fp.ctl = cv.take(kCtlWords * 4);
+  fp.code = cv.take((size_t)n * 4);
+  fp.sel = cv.take((size_t)l * 4);
+  fp.twf = cv.take((size_t)std::max(1, s / 2) * 16);
+  fp.twp = cv.take((size_t)std::max(1, s / 2) * 16);
+}
+
+size_t precision_scratch_bytes(int64_t m, int64_t n, int l, int precision, int num_cu);
+
+rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_params *p, FactorPlan *fp) {
+  std::string why;
+  fp->m = A->m;
+  fp->n = A->n;
+  fp->l = p->l;
+  fp->s = p->s;
+  if (!plan_gepp(A->m, p->l, cx.caps, &fp->py, &why)) return fail(RLU_ERR_INVALID_ARG, "row-pivoted LU: %s", why.c_str());
+  if (!plan_gepp(A->n, p->l, cx.caps, &fp->pb, &why)) return fail(RLU_ERR_INVALID_ARG, "column-pivoted LU: %s", why.c_str());
+  const int64_t m = A->m, n = A->n;
+  const int l = p->l;
+  fp->splits_w = choose_splits(n, l, m, cx.caps.num_cu);
+  fp->splits_g = choose_splits(l, l, m, cx.caps.num_cu);
+  Carver cv;
+  plan_sketch_part(cv, *fp, n, l, p->s);
+  fp->sketch_total = cv.off;
+  fp->Y = cv.take((size_t)m * l * 8);
+  fp->Wk = cv.take((fp->py.multi || fp->pb.multi) ? (size_t)std::max(m, n) * l * 8 : 0);
+  fp->slots = cv.take(std::max(gepp_workspace_bytes(m, l, fp->py), gepp_workspace_bytes(n, l, fp->pb)));
+  fp->Lhat = cv.take((size_t)m * l * 8);
+  fp->Uy = cv.take((size_t)l * l * 8);
+  fp->Wt = cv.take((size_t)n * l * 8);
+  fp->parts = cv.take(std::max(gemm_f64_splitk_scratch(n, l, fp->splits_w),
+                               gemm_f64_splitk_scratch(l, l, fp->splits_g)));
+  fp->Gm = cv.take((size_t)l * l * 8);
+  fp->Linv = cv.take((size_t)l * l * 8);
+  fp->Ginv = cv.take((size_t)l * l * 8);
+  fp->Bt = cv.take((size_t)n * l * 8);
+  fp->Lph = cv.take((size_t)n * l * 8);
+  fp->Up = cv.take((size_t)l * l * 8);
+  fp->Lt = cv.take((size_t)l * l * 8);
+  fp->prec = cv.take(p->precision == RLU_PREC_F64 ? 0 : precision_scratch_bytes(m, n, l, p->precision, cx.caps.num_cu));
+  fp->total = cv.off;
+  return RLU_OK;
+}
+
+template <typename T>
+static T *at(void *ws, size_t off) { return reinterpret_cast<T *>(reinterpret_cast<char *>(ws) + off); }
+
+// ---------------------------------------------------------------------------
+// stages
+// ---------------------------------------------------------------------------
+static rlu_status run_params(const FactorPlan &fp, const rlu_params *p, void *ws, hipStream_t st) {
+  launch_sem_codes(fp.n, p->s, p->seed, at<uint32_t>(ws, fp.code), nullptr, nullptr, st);
+  launch_srft_params(p->s, p->l, p->seed, nullptr, at<int32_t>(ws, fp.sel), at<double2>(ws, fp.twf),
+                     at<double2>(ws, fp.twp), st);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? RLU_OK : hip_fail(e, "parameter kernels");
+}
+
+hipError_t launch_csr_check(const rlu_matrix *A, int validate_cols, rlu_info *info, hipStream_t st);
+
+static rlu_status run_sketch(const rlu_ctx_impl &cx, const FactorPlan &fp, const rlu_matrix *A,
+                             const rlu_params *p, double *Y, int64_t ldy, void *ws, rlu_info *info,
+                             hipStream_t st) {
+  hipError_t e;
+  if (A->layout == RLU_DENSE_ROW_MAJOR) {
+    e = launch_sketch_dense(A->m, A->n, A->values, A->dtype, A->ld, p->s, p->l, at<uint32_t>(ws, fp.code),
+                            at<int32_t>(ws, fp.sel), at<double2>(ws, fp.twf), at<double2>(ws, fp.twp),
+                            Y, ldy, cx.caps.num_cu, st);
+  } else {
+    if (info) {
+      e = launch_csr_check(A, (p->flags & RLU_FLAG_VALIDATE) != 0, info, st);
+      if (e != hipSuccess) return hip_fail(e, "CSR check");
+    }
+    e = launch_sketch_csr(A->m, A->n, A->row_ptr, A->col_idx, (const double *)A->values, p->s, p->l,
+                          at<uint32_t>(ws, fp.code), at<int32_t>(ws, fp.sel), at<double2>(ws, fp.twf),
+                          at<double2>(ws, fp.twp), Y, ldy, info ? &info->bad_index : nullptr,
+                          cx.caps.num_cu, st);
+  }
+  return e == hipSuccess ? RLU_OK : hip_fail(e, "sketch kernel");
+}
+
+hipError_t contraction_csr(int64_t m, int64_t n, int l, const int32_t *row_ptr, const int32_t *col,
+                           const double *val, const double *Lhat, double *Wt, hipStream_t st);
+rlu_status run_precision_contraction(const rlu_ctx_impl &cx, const FactorPlan &fp, const rlu_matrix *A,
+                                     const rlu_params *p, void *ws, hipStream_t st);
+
+// Stage-boundary events of one timed call (no-ops when timing is off).
+struct StageMarks {
+  std::array<hipEvent_t, RLU_NUM_STAGES + 1> ev{};
+  bool on = false;
+  hipStream_t st = nullptr;
+  void mark(int i) {
+    if (on) hipEventRecord(ev[i], st);
+  }
+};
+
+static rlu_status begin_timing(rlu_ctx_impl &cx, StageMarks &sm, hipStream_t st) {
+  StageTimer &t = cx.timer;
+  while (t.pool.size() < t.used + RLU_NUM_STAGES + 1) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return hip_fail(err, "hipEventCreate");
+    t.pool.push_back(e);
+  }
+  for (int i = 0; i <= RLU_NUM_STAGES; ++i) sm.ev[i] = t.pool[t.used + i];
+  t.used += RLU_NUM_STAGES + 1;
+  t.calls.push_back(sm.ev);
+  sm.on = true;
+  sm.st = st;
+  return RLU_OK;
+}
+
+rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_params *p,
+                          const rlu_factors *out, void *ws, const FactorPlan &fp, hipStream_t st) {
+  const int64_t m = A->m, n = A->n;
+  const int l = p->l;
+  hipError_t e;
+  StageMarks sm;
+  if (p->flags & RLU_FLAG_TIMING) {
+    rlu_status ts = begin_timing(cx, sm, st);
+    if (ts != RLU_OK) return ts;
+  }
+  sm.mark(RLU_STAGE_PARAMS);
+  rlu_info *info = out->info;
+  uint32_t *ctl = at<uint32_t>(ws, fp.ctl);
+  int32_t *abort_flag = reinterpret_cast<int32_t *>(ctl + 1);
+
+  if ((e = launch_fill_u32(ctl, 0u, kCtlWords, st)) != hipSuccess) return hip_fail(e, "fill");
+  if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(info), 0u, sizeof(rlu_info) / 4, st)) != hipSuccess)
+    return hip_fail(e, "fill");
+  rlu_status rs = run_params(fp, p, ws, st);
+  if (rs != RLU_OK) return rs;
+
+  double *Y = out->Y ? out->Y : at<double>(ws, fp.Y);
+  const int64_t ldy = out->Y ? out->ldy : l;
+  sm.mark(RLU_STAGE_SKETCH);
+  if ((rs = run_sketch(cx, fp, A, p, Y, ldy, ws, info, st)) != RLU_OK) return rs;
+
+  // Step 3: P Y = L_y U_y (rows of L_y kept in A's order: Lhat = P^T L_y)
+  double *Lhat = at<double>(ws, fp.Lhat);
+  double *Uy = out->Uy ? out->Uy : at<double>(ws, fp.Uy);
+  sm.mark(RLU_STAGE_LU_Y);
+  e = launch_gepp(m, l, Y, ldy, at<double>(ws, fp.Wk), Lhat, Uy, out->perm_r, out->ipiv_r,
+                  at<void>(ws, fp.slots), ctl + 0, abort_flag, info, 0, fp.py, st);
+  if (e != hipSuccess) return hip_fail(e, "row-pivoted LU launch");
+
+  // Step 4: W^T = A^T Lhat (n x l) and G = Lhat^T Lhat
+  double *Wt = at<double>(ws, fp.Wt);
+  sm.mark(RLU_STAGE_CONTRACT);
+  if (A->layout == RLU_CSR) {
+    e = contraction_csr(m, n, l, A->row_ptr, A->col_idx, (const double *)A->values, Lhat, Wt, st);
+    if (e != hipSuccess) return hip_fail(e, "sparse contraction");
+  } else if (p->precision == RLU_PREC_F64) {
+    GemmArgs g{};
+    g.M = n; g.N = l; g.K = m;
+    g.A = A->values; g.lda = A->ld; g.a_dtype = A->dtype; g.trans_a = true;
+    g.B = Lhat; g.ldb = l;
+    g.C = Wt; g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
+    e = gemm_f64_splitk(g, fp.splits_w, at<double>(ws, fp.parts), st);
+    if (e != hipSuccess) return hip_fail(e, "contraction");
+  }
+  sm.mark(RLU_STAGE_GRAM);
+  {
+    GemmArgs g{};
+    g.M = l; g.N = l; g.K = m;
+    g.A = Lhat; g.lda = l; g.a_dtype = RLU_F64; g.trans_a = true;
+    g.B = Lhat; g.ldb = l;
+    g.C = at<double>(ws, fp.Gm); g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
+    e = gemm_f64_splitk(g, fp.splits_g, at<double>(ws, fp.parts), st);
+    if (e != hipSuccess) return hip_fail(e, "Gram matrix");
+  }
+  sm.mark(RLU_STAGE_CHOL);
+  if ((e = launch_chol_inv(l, at<double>(ws, fp.Gm), at<double>(ws, fp.Linv), info, st)) != hipSuccess)
+    return hip_fail(e, "Cholesky");
+  {  // G^{-1} = Linv^T Linv
+    GemmArgs g{};
+    g.M = l; g.N = l; g.K = l;
+    g.A = at<double>(ws, fp.Linv); g.lda = l; g.a_dtype = RLU_F64; g.trans_a = true;
+    g.B = at<double>(ws, fp.Linv); g.ldb = l;
+    g.C = at<double>(ws, fp.Ginv); g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
+    if ((e = gemm_f64(g, st)) != hipSuccess) return hip_fail(e, "inverse Gram");
+  }
+  sm.mark(RLU_STAGE_SOLVE);
+  if (A->layout == RLU_DENSE_ROW_MAJOR && p->precision != RLU_PREC_F64) {
+    // reduced-precision contraction with one refinement step; writes Bt
+    if ((rs = run_precision_contraction(cx, fp, A, p, ws, st)) != RLU_OK) return rs;
+  } else {  // B^T = W^T G^{-1}
+    GemmArgs g{};
+    g.M = n; g.N = l; g.K = l;
+    g.A = Wt; g.lda = l; g.a_dtype = RLU_F64; g.trans_a = false;
+    g.B = at<double>(ws, fp.Ginv); g.ldb = l;
+    g.C = at<double>(ws, fp.Bt); g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
+    if ((e = gemm_f64(g, st)) != hipSuccess) return hip_fail(e, "least-squares product");
+  }
+  double *Bt = at<double>(ws, fp.Bt);
+  if (out->B) {
+    if ((e = launch_transpose(n, l, Bt, l, out->B, n, st)) != hipSuccess) return hip_fail(e, "transpose");
+  }
+
+  // Step 5: B Q = L~ U through the row-pivoted LU of B^T
+  double *Lph = at<double>(ws, fp.Lph), *Up = at<double>(ws, fp.Up), *Lt = at<double>(ws, fp.Lt);
+  sm.mark(RLU_STAGE_LU_B);
+  e = launch_gepp(n, l, Bt, l, at<double>(ws, fp.Wk), Lph, Up, out->perm_c, out->ipiv_c,
+                  at<void>(ws, fp.slots), ctl + 2, abort_flag, info, 1, fp.pb, st);
+  if (e != hipSuccess) return hip_fail(e, "column-pivoted LU launch");
+  sm.mark(RLU_STAGE_ASSEMBLE);
+  if ((e = launch_ltilde(l, Up, Lt, st)) != hipSuccess) return hip_fail(e, "L~");
+  if ((e = launch_assemble_u(l, n, Up, Lph, out->perm_c, out->U, out->ldu, st)) != hipSuccess)
+    return hip_fail(e, "U");
+
+  // Step 6: L = L_y L~ = (P Lhat) L~
+  {
+    GemmArgs g{};
+    g.M = m; g.N = l; g.K = l;
+    g.A = Lhat; g.lda = l; g.a_dtype = RLU_F64; g.trans_a = false; g.gather = out->perm_r;
+    g.B = Lt; g.ldb = l;
+    g.C = out->L; g.ldc = out->ldl; g.alpha = 1.0; g.beta = 0.0;
+    if ((e = gemm_f64(g, st)) != hipSuccess) return hip_fail(e, "L = L_y L~");
+  }
+  if ((e = launch_finalize(info, abort_flag, st)) != hipSuccess) return hip_fail(e, "finalize");
+  sm.mark(RLU_NUM_STAGES);
+  return RLU_OK;
+}
+
+}  // namespace rlu
+
+using namespace rlu;
+
+// ---------------------------------------------------------------------------
+// exported C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *rlu_last_error(void) { return g_last_error.c_str(); }
+
+rlu_status rlu_create(int device, rlu_ctx **ctx) {
+  if (!ctx) return fail(RLU_ERR_INVALID_ARG, "ctx out-pointer is NULL");
+  *ctx = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (device < 0 || device >= count) return fail(RLU_ERR_INVALID_ARG, "device %d out of range (%d devices)", device, count);
+  if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipDeviceProp_t prop;
+  if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(RLU_ERR_DEVICE, "device %d is %s; this library is built for gfx950 only", device, prop.gcnArchName);
+  int coop = 0;
+  hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device);
+  if (!coop) return fail(RLU_ERR_DEVICE, "device %d does not support cooperative launches", device);
+  rlu_ctx_impl *c = new (std::nothrow) rlu_ctx_impl();
+  if (!c) return fail(RLU_ERR_NO_MEMORY, "host allocation failed");
+  c->caps.device = device;
+  c->caps.num_cu = prop.multiProcessorCount;
+  c->caps.max_lds = prop.sharedMemPerBlockOptin ? prop.sharedMemPerBlockOptin : prop.sharedMemPerBlock;
+  sketch_dense_set_attrs();
+  *ctx = reinterpret_cast<rlu_ctx *>(c);
+  return RLU_OK;
+}
+
+rlu_status rlu_destroy(rlu_ctx *ctx) {
+  if (!ctx) return RLU_OK;
+  rlu_ctx_impl *c = reinterpret_cast<rlu_ctx_impl *>(ctx);
+  serve_shutdown(*c);
+  for (hipEvent_t e : c->timer.pool) hipEventDestroy(e);
+  delete c;
+  return RLU_OK;
+}
+
+rlu_status rlu_workspace_size(rlu_ctx *ctx, const rlu_matrix *A, const rlu_params *p, size_t *bytes) {
+  if (!ctx || !bytes) return fail(RLU_ERR_INVALID_ARG, "NULL argument");
+  rlu_status st = validate_matrix(A);
+  if (st != RLU_OK) return st;
+  if ((st = validate_params(A, p)) != RLU_OK) return st;
+  FactorPlan fp;
+  if ((st = plan_factor(*reinterpret_cast<rlu_ctx_impl *>(ctx), A, p, &fp)) != RLU_OK) return st;
+  *bytes = fp.total;
+  return RLU_OK;
+}
+
+rlu_status rlu_sketch_params(const rlu_params *p, int64_t n, int32_t *h, int8_t *sgn, int8_t *d,
+                             int32_t *sel, void *stream) {
+  rlu_status st = validate_params(nullptr, p);
+  if (st != RLU_OK) return st;
+  if (n < 1) return fail(RLU_ERR_INVALID_ARG, "n must be >= 1");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (h || sgn) launch_sem_codes(n, p->s, p->seed, nullptr, h, sgn, s);
+  if (d || sel) launch_srft_params(p->s, p->l, p->seed, d, sel, nullptr, nullptr, s);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? RLU_OK : hip_fail(e, "parameter kernels");
+}
+
+rlu_status rlu_sketch(rlu_ctx *ctx, const rlu_matrix *A, const rlu_params *p, double *Y, int64_t ldy,
+                      void *ws, size_t ws_bytes, void *stream) {
+  if (!ctx) return fail(RLU_ERR_INVALID_ARG, "ctx is NULL");
+  rlu_ctx_impl &cx = *reinterpret_cast<rlu_ctx_impl *>(ctx);
+  rlu_status st = validate_matrix(A);
+  if (st != RLU_OK) return st;
+  if ((st = validate_params(A, p)) != RLU_OK) return st;
+  if (!Y) return fail(RLU_ERR_INVALID_ARG, "Y is NULL");
+  if (ldy < p->l) return fail(RLU_ERR_INVALID_ARG, "ldy (%lld) < l (%d)", (long long)ldy, p->l);
+  FactorPlan fp;
+  Carver cv;
+  plan_sketch_part(cv, fp, A->n, p->l, p->s);
+  fp.n = A->n;
+  fp.m = A->m;
+  if (!ws || ws_bytes < cv.off || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(RLU_ERR_NO_MEMORY, "workspace must be 256-byte aligned and hold %zu bytes", cv.off);
+  hipError_t e = hipSetDevice(cx.caps.device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if ((st = run_params(fp, p, ws, s)) != RLU_OK) return st;
+  return run_sketch(cx, fp, A, p, Y, ldy, ws, nullptr, s);
+}
+
+rlu_status rlu_factor(rlu_ctx *ctx, const rlu_matrix *A, const rlu_params *p, const rlu_factors *out,
+                      void *ws, size_t ws_bytes, void *stream) {
+  if (!ctx) return fail(RLU_ERR_INVALID_ARG, "ctx is NULL");
+  rlu_ctx_impl &cx = *reinterpret_cast<rlu_ctx_impl *>(ctx);
+  rlu_status st = validate_matrix(A);
+  if (st != RLU_OK) return st;
+  if ((st = validate_params(A, p)) != RLU_OK) return st;
+  if ((st = validate_factors(A, p, out)) != RLU_OK) return st;
+  FactorPlan fp;
+  if ((st = plan_factor(cx, A, p, &fp)) != RLU_OK) return st;
+  if (!ws || ws_bytes < fp.total || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(RLU_ERR_NO_MEMORY, "workspace must be 256-byte aligned and hold %zu bytes", fp.total);
+  hipError_t e = hipSetDevice(cx.caps.device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  return factor_enqueue(cx, A, p, out, ws, fp, reinterpret_cast<hipStream_t>(stream));
+}
+
+rlu_status rlu_stage_times(rlu_ctx *ctx, float *ms, int *calls) {
+  if (!ctx || !ms) return fail(RLU_ERR_INVALID_ARG, "NULL argument");
+  rlu_ctx_impl &cx = *reinterpret_cast<rlu_ctx_impl *>(ctx);
+  for (int i = 0; i < RLU_NUM_STAGES; ++i) ms[i] = 0.f;
+  StageTimer &t = cx.timer;
+  for (auto &ev : t.calls) {
+    hipError_t e = hipEventSynchronize(ev[RLU_NUM_STAGES]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    for (int i = 0; i < RLU_NUM_STAGES; ++i) {
+      float v = 0.f;
+      if ((e = hipEventElapsedTime(&v, ev[i], ev[i + 1])) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+      ms[i] += v;
+    }
+  }
+  if (calls) *calls = (int)t.calls.size();
+  t.calls.clear();
+  t.used = 0;
+  return RLU_OK;
+}
+
+rlu_status rlu_tall_lu_workspace_size(rlu_ctx *ctx, int64_t rows, int64_t cols, size_t *bytes) {
+  if (!ctx || !bytes) return fail(RLU_ERR_INVALID_ARG, "NULL argument");
+  if (cols < 1 || rows < cols || cols > kMaxL || rows > INT32_MAX)
+    return fail(RLU_ERR_INVALID_ARG, "need 1 <= cols <= rows, cols <= %d", kMaxL);
+  rlu_ctx_impl &cx = *reinterpret_cast<rlu_ctx_impl *>(ctx);
+  GeppPlan gp;
+  std::string why;
+  if (!plan_gepp(rows, (int)cols, cx.caps, &gp, &why)) return fail(RLU_ERR_INVALID_ARG, "%s", why.c_str());
+  Carver cv;
+  cv.take(kCtlWords * 4);
+  cv.take(gepp_workspace_bytes(rows, (int)cols, gp));
+  cv.take(gp.multi ? (size_t)rows * cols * 8 : 0);
+  *bytes = cv.off;
+  return RLU_OK;
+}
+
+rlu_status rlu_tall_lu(rlu_ctx *ctx, const double *X, int64_t rows, int64_t cols, int64_t ldx, double *Lhat,
+                       double *U, int32_t *perm, int32_t *ipiv, rlu_info *info, void *ws, size_t ws_bytes,
+                       void *stream) {
+  size_t need = 0;
+  rlu_status st = rlu_tall_lu_workspace_size(ctx, rows, cols, &need);
+  if (st != RLU_OK) return st;
+  if (!X || !Lhat || !U || !perm || !info) return fail(RLU_ERR_INVALID_ARG, "NULL matrix argument");
+  if (ldx < cols) return fail(RLU_ERR_INVALID_ARG, "ldx < cols");
+  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(RLU_ERR_NO_MEMORY, "workspace must be 256-byte aligned and hold %zu bytes", need);
+  rlu_ctx_impl &cx = *reinterpret_cast<rlu_ctx_impl *>(ctx);
+  GeppPlan gp;
+  std::string why;
+  plan_gepp(rows, (int)cols, cx.caps, &gp, &why);
+  Carver cv;
+  const size_t o_ctl = cv.take(kCtlWords * 4);
+  const size_t o_slots = cv.take(gepp_workspace_bytes(rows, (int)cols, gp));
+  const size_t o_wk = cv.take(gp.multi ? (size_t)rows * cols * 8 : 0);
+  hipError_t e = hipSetDevice(cx.caps.device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  uint32_t *ctl = at<uint32_t>(ws, o_ctl);
+  if ((e = launch_fill_u32(ctl, 0u, kCtlWords, s)) != hipSuccess) return hip_fail(e, "fill");
+  if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(info), 0u, sizeof(rlu_info) / 4, s)) != hipSuccess)
+    return hip_fail(e, "fill");
+  e = launch_gepp(rows, (int)cols, X, ldx, at<double>(ws, o_wk), Lhat, U, perm, ipiv, at<void>(ws, o_slots),
+                  ctl, reinterpret_cast<int32_t *>(ctl + 1), info, 0, gp, s);
+  if (e != hipSuccess) return hip_fail(e, "tall LU launch");
+  if ((e = launch_finalize(info, reinterpret_cast<int32_t *>(ctl + 1), s)) != hipSuccess) return hip_fail(e, "finalize");
+  return RLU_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,123 @@
+// Host-side internals of the library: launchers and small helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <array>
+#include <string>
+#include <vector>
+
+#include "rlu.h"
+
+namespace rlu {
+
+inline int ilog2_exact(int64_t v) {
+  int b = 0;
+  while ((int64_t(1) << b) < v) ++b;
+  return b;
+}
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+constexpr int kMaxS = 8192;            // LDS-resident transform: 16 s bytes per block
+constexpr int kSketchThreads = 256;
+
+// ---- parameters -----------------------------------------------------------
+void launch_sem_codes(int64_t n, int s, uint64_t seed, uint32_t *code, int32_t *h, int8_t *sgn,
+                      hipStream_t st);
+void launch_srft_params(int s, int l, uint64_t seed, int8_t *d, int32_t *sel, double2 *twf,
+                        double2 *twp, hipStream_t st);
+
+// ---- sketch -----------------------------------------------------------------
+struct SketchPlan {
+  int grid;  // blocks of the dense sketch
+};
+hipError_t launch_sketch_dense(int64_t m, int64_t n, const void *A, int dtype, int64_t lda, int s,
+                               int l, const uint32_t *code, const int32_t *sel,
+                               const double2 *twf, const double2 *twp, double *Y, int64_t ldy,
+                               int num_cu, hipStream_t st);
+hipError_t launch_sketch_csr(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t *col,
+                             const double *val, int s, int l, const uint32_t *code,
+                             const int32_t *sel, const double2 *twf, const double2 *twp,
+                             double *Y, int64_t ldy, int32_t *bad_index, int num_cu,
+                             hipStream_t st);
+
+// ---- tall pivoted LU (cooperative) ---------------------------------------------
+struct GeppPlan {
+  int G;         // blocks (co-resident)
+  int R;         // rows per block
+  int nb;        // panel width
+  int slot_stride;
+  size_t lds;    // dynamic LDS bytes
+  bool multi;    // more than one panel
+};
+struct DevCaps {
+  int device;
+  int num_cu;
+  size_t max_lds;  // dynamic LDS bytes a block may use
+};
+bool plan_gepp(int64_t rows, int cols, const DevCaps &caps, GeppPlan *plan, std::string *why);
+size_t gepp_workspace_bytes(int64_t rows, int cols, const GeppPlan &plan);
+// X: rows x cols (ldx); work: rows x cols scratch when plan.multi; slots and
+// control words come from `ws` (gepp_workspace_bytes); ctl points at two
+// zeroed words (barrier counter, abort flag).
+hipError_t launch_gepp(int64_t rows, int cols, const double *X, int64_t ldx, double *work,
+                       double *Lhat, double *U, int32_t *perm, int32_t *ipiv, void *ws,
+                       uint32_t *bar_counter, int32_t *abort_flag, rlu_info *info, int which,
+                       const GeppPlan &plan, hipStream_t st);
+
+// ---- FP64 GEMM on MFMA ------------------------------------------------------------
+// C (M x N, ldc) = alpha * op(A) * op(B) + beta * C, or split-K partials.
+struct GemmArgs {
+  int64_t M, N, K;
+  const void *A; int64_t lda; int a_dtype; bool trans_a; const int32_t *gather;
+  const double *B; int64_t ldb; bool trans_b;
+  double *C; int64_t ldc;
+  double alpha, beta;
+};
+// Plain (no split): writes C directly.
+hipError_t gemm_f64(const GemmArgs &g, hipStream_t st);
+// Split-K: partials into `parts` (splits x M x N), then reduced into C
+// (C = alpha * sum + beta * C).  Returns the scratch bytes needed when
+// parts == nullptr (no launch).
+size_t gemm_f64_splitk_scratch(int64_t M, int64_t N, int splits);
+hipError_t gemm_f64_splitk(const GemmArgs &g, int splits, double *parts, hipStream_t st);
+int choose_splits(int64_t M, int64_t N, int64_t K, int num_cu);
+
+// ---- small dense FP64 pieces ---------------------------------------------------------
+// In place: G (l x l, ld l, SPD) -> Linv = inverse of the Cholesky factor
+// (G = L L^T), written to Linv (l x l, lower, zeros above).
+hipError_t launch_chol_inv(int l, double *G, double *Linv, rlu_info *info, hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t st);
+hipError_t launch_ltilde(int l, const double *Up, double *Lt, hipStream_t st);
+hipError_t launch_assemble_u(int l, int64_t n, const double *Up, const double *Lphat,
+                             const int32_t *perm_c, double *U, int64_t ldu, hipStream_t st);
+hipError_t launch_transpose(int64_t rows, int64_t cols, const double *in, int64_t ldin, double *out,
+                            int64_t ldout, hipStream_t st);
+hipError_t launch_copy_rows(int64_t rows, int64_t cols, const double *in, int64_t ldin,
+                            double *out, int64_t ldout, hipStream_t st);
+hipError_t launch_finalize(rlu_info *info, const int32_t *abort_flag, hipStream_t st);
+
+// ---- context, errors, validation ---------------------------------------------------
+struct ServeState;
+// HIP events of stage boundaries for calls made with RLU_FLAG_TIMING.
+struct StageTimer {
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<std::array<hipEvent_t, RLU_NUM_STAGES + 1>> calls;
+};
+struct rlu_ctx_impl {
+  DevCaps caps{};
+  ServeState *serve = nullptr;
+  StageTimer timer;
+};
+rlu_status fail(rlu_status st, const char *fmt, ...);
+rlu_status hip_fail(hipError_t e, const char *what);
+rlu_status validate_matrix(const rlu_matrix *A);
+rlu_status validate_params(const rlu_matrix *A, const rlu_params *p);
+rlu_status validate_factors(const rlu_matrix *A, const rlu_params *p, const rlu_factors *out);
+void serve_shutdown(rlu_ctx_impl &cx);
+
+}  // namespace rlu

@@ -1,0 +1,240 @@
+"""GPU parity of the dense path against the oracle (Algorithm 1, exact
+least-squares product).
+
+Bars: integer parameters and pivot sequences bit-exact (inputs screened so
+every pivot's top-two relative gap is >= 1e-5 in the oracle); Y within 1e-10
+relative (Frobenius); L columns / U rows whose growth factor rho_j =
+|d_0| / |d_j| stays <= 1e4 within 1e-10 relative per column / row (rounding
+in later columns is amplified by rho_j); everything else through the
+product, ||L_g U_g - L_o U_o||_F <= 1e-10 ||A||_F.  On a well-conditioned
+input (sigma_i = 1/i, rank >= l) the 1e-10 bar holds for every column.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1601_04280_amd as rlu
+import synth
+from oracle import rlu as R
+from oracle import rng as orng
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def rel_fro(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# ---------------------------------------------------------------- parameters
+
+@pytest.mark.parametrize("n,l,s,seed", [(512, 30, 256, 1), (1000, 2, 2, 3), (5000, 210, 2048, 2**64 - 5),
+                                        (3, 1, 4, 0), (17000, 520, 4096, 12345)])
+def test_params_bit_exact(n, l, s, seed):
+    if l > s:
+        pytest.skip("l > s")
+    h, sgn, d, sel = rlu.sketch_params(n, l, s, seed)
+    oh, osgn = orng.sem_hash(seed, n, s)
+    np.testing.assert_array_equal(h.cpu().numpy(), oh)
+    np.testing.assert_array_equal(sgn.cpu().numpy(), osgn)
+    np.testing.assert_array_equal(d.cpu().numpy(), orng.srft_signs(seed, s))
+    np.testing.assert_array_equal(sel.cpu().numpy(), orng.srft_select(seed, s, l))
+
+
+# ---------------------------------------------------------------- sketch
+
+@pytest.mark.parametrize("m,n,l,s,seed,dtype", [
+    (1024, 512, 30, 256, 1, np.float64),
+    (37, 1000, 20, 64, 5, np.float64),        # ragged rows and columns
+    (300, 2049, 64, 2048, 7, np.float64),     # odd log2(s/2): radix-2 stage
+    (64, 300, 2, 2, 9, np.float64),           # s = 2: trivial transform
+    (200, 777, 40, 128, 11, np.float32),      # FP32 storage widened exactly
+    (20, 8192, 100, 8192, 13, np.float64),    # largest s
+])
+def test_sketch_matches_oracle(m, n, l, s, seed, dtype):
+    a = np.random.default_rng(seed).standard_normal((m, n)).astype(dtype)
+    Y = rlu.sketch(to_dev(a), k=1, l=l, s=s, seed=seed).cpu().numpy()
+    ref = R.sketch_y(a.astype(np.float64), R.Params(1, l, s, seed))
+    assert rel_fro(Y, ref) <= 1e-10
+    assert np.abs(Y - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_sketch_respects_leading_dimension():
+    a = np.random.default_rng(3).standard_normal((50, 300))
+    big = torch.zeros(50, 320, dtype=torch.float64, device=DEV)
+    big[:, :300] = to_dev(a)
+    Y = rlu.sketch(big[:, :300], k=1, l=16, s=64, seed=4).cpu().numpy()
+    ref = R.sketch_y(a, R.Params(1, 16, 64, 4))
+    assert rel_fro(Y, ref) <= 1e-10
+
+
+# ---------------------------------------------------------------- tall LU
+
+def screened_gaussian(rows, cols, seed):
+    from oracle import lu
+    for s in range(seed, seed + 50):
+        y = np.random.default_rng(s).standard_normal((rows, cols))
+        res = lu.gepp(y)
+        if res[5] >= 1e-5:
+            return y, res
+    raise RuntimeError("no screened input found")
+
+
+@pytest.mark.parametrize("rows,cols,seed", [(40, 30, 1), (1000, 64, 2), (4099, 33, 3), (16384, 210, 4),
+                                            (20000, 300, 5)])
+def test_tall_lu_matches_oracle(rows, cols, seed):
+    y, (L, U, perm, ipiv, zp, gap) = screened_gaussian(rows, cols, seed)
+    Lhat, Ug, permg, ipivg, info = rlu.tall_lu(to_dev(y))
+    np.testing.assert_array_equal(ipivg.cpu().numpy(), ipiv)
+    np.testing.assert_array_equal(permg.cpu().numpy(), perm)
+    Lg = Lhat.cpu().numpy()[perm]           # Lhat is in X's own row order
+    np.testing.assert_allclose(Lg, L, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(Ug.cpu().numpy(), U, rtol=0, atol=1e-12 * np.abs(U).max())
+    assert int(info[1].item()) == zp == 0
+
+
+def test_tall_lu_zero_columns():
+    # pivot -64 (a power of two) makes every multiplier and product exact, so
+    # the Schur column 3 (= 2 x column 0) is exactly zero on both sides
+    y = np.zeros((100, 8))
+    y[:, 0] = (np.arange(100) % 97) - 64.0
+    y[:, 3] = 2.0 * y[:, 0]
+    from oracle import lu
+    L, U, perm, ipiv, zp, _ = lu.gepp(y)
+    Lhat, Ug, permg, ipivg, info = rlu.tall_lu(to_dev(y))
+    assert int(info[1].item()) == zp == 7
+    np.testing.assert_array_equal(ipivg.cpu().numpy(), ipiv)
+    np.testing.assert_array_equal(permg.cpu().numpy(), perm)
+    np.testing.assert_array_equal(Lhat.cpu().numpy()[perm], L)
+    np.testing.assert_array_equal(Ug.cpu().numpy(), U)
+
+
+# ---------------------------------------------------------------- factor
+
+def growth(diag):
+    d = np.abs(diag)
+    return d[0] / np.where(d > 0, d, np.inf)
+
+
+def compare_factors(A, g, o, check_all_columns=False):
+    """g: rlu.Factorization (device), o: oracle Result."""
+    np.testing.assert_array_equal(g.perm_r.cpu().numpy(), o.perm_r)
+    np.testing.assert_array_equal(g.perm_c.cpu().numpy(), o.perm_c)
+    np.testing.assert_array_equal(g.ipiv_r.cpu().numpy(), o.ipiv_r)
+    np.testing.assert_array_equal(g.ipiv_c.cpu().numpy(), o.ipiv_c)
+    Lg, Ug = g.L.cpu().numpy(), g.U.cpu().numpy()
+    if g.Y is not None:
+        assert rel_fro(g.Y.cpu().numpy(), o.Y) <= 1e-10
+    rho_l = growth(np.diag(o.Uy))
+    rho_u = growth(np.diag(o.U))
+    for j in range(o.L.shape[1]):
+        if check_all_columns or rho_l[j] <= 1e4:
+            assert rel_fro(Lg[:, j], o.L[:, j]) <= 1e-10, (j, rel_fro(Lg[:, j], o.L[:, j]))
+        if check_all_columns or rho_u[j] <= 1e4:
+            assert rel_fro(Ug[j], o.U[j]) <= 1e-10, (j, rel_fro(Ug[j], o.U[j]))
+    assert np.linalg.norm(Lg @ Ug - o.L @ o.U) <= 1e-10 * np.linalg.norm(A)
+
+
+def screened_factor(A, k, l, s, seed):
+    for sd in range(seed, seed + 20):
+        o = R.rlu(A, R.Params(k, l, s, sd))
+        if o.min_gap_y >= 1e-5 and o.min_gap_b >= 1e-5:
+            return sd, o
+    raise RuntimeError("no screened seed")
+
+
+def test_factor_small_lowrank_plus_noise():
+    A = synth.small_dense()
+    seed, o = screened_factor(A, 20, 30, 256, 1)
+    g = rlu.factor(to_dev(A), k=20, l=30, s=256, seed=seed, keep_intermediates=True)
+    compare_factors(A, g, o)
+    info = g.info_dict()
+    assert info["status"] == 0 and info["zero_pivots_y"] == 0 and info["zero_pivots_b"] == 0
+    assert rel_fro(g.B.cpu().numpy(), o.B) <= 1e-9
+
+
+def test_factor_well_conditioned_all_columns():
+    A = synth.lowrank_dense(800, 600, 1.0 / np.arange(1, 61), 77)
+    seed, o = screened_factor(A, 40, 48, 128, 3)
+    g = rlu.factor(to_dev(A), k=40, l=48, s=128, seed=seed, keep_intermediates=True)
+    compare_factors(A, g, o, check_all_columns=True)
+
+
+@pytest.mark.parametrize("m,n,k,l,s", [(16, 16, 16, 16, 16), (33, 700, 5, 17, 32), (900, 35, 10, 35, 64),
+                                       (3000, 2000, 100, 150, 1024)])
+def test_factor_shapes(m, n, k, l, s):
+    A = np.random.default_rng(m + n).standard_normal((m, n))
+    seed, o = screened_factor(A, k, l, s, 5)
+    g = rlu.factor(to_dev(A), k=k, l=l, s=s, seed=seed, keep_intermediates=True)
+    compare_factors(A, g, o)
+
+
+def test_factor_rank_exact_and_identity():
+    A = synth.lowrank_dense(2000, 1500, np.linspace(1, 0.1, 40), 8)
+    g = rlu.factor(to_dev(A), k=40, l=50, s=256, seed=3)
+    L, U = g.L.cpu().numpy(), g.U.cpu().numpy()
+    pr, pc = g.perm_r.cpu().numpy(), g.perm_c.cpu().numpy()
+    assert np.linalg.norm(L @ U - A[np.ix_(pr, pc)]) <= 1e-12 * np.linalg.norm(A)
+
+
+def test_factor_zero_matrix():
+    A = np.zeros((64, 48))
+    o = R.rlu(A, R.Params(4, 8, 16, 1))
+    g = rlu.factor(to_dev(A), k=4, l=8, s=16, seed=1)
+    info = g.info_dict()
+    assert info["zero_pivots_y"] == o.zero_pivots_y == 8
+    assert info["zero_pivots_b"] == o.zero_pivots_b == 8
+    np.testing.assert_array_equal(g.perm_r.cpu().numpy(), o.perm_r)
+    np.testing.assert_array_equal(g.perm_c.cpu().numpy(), o.perm_c)
+    np.testing.assert_array_equal(g.L.cpu().numpy(), o.L)
+    np.testing.assert_array_equal(g.U.cpu().numpy(), o.U)
+
+
+def test_factor_float32_storage():
+    A = synth.lowrank_dense(1200, 900, np.exp(-np.arange(1, 301) / 30.0), 4).astype(np.float32)
+    A64 = A.astype(np.float64)
+    seed, o = screened_factor(A64, 50, 60, 512, 2)
+    g = rlu.factor(to_dev(A), k=50, l=60, s=512, seed=seed, keep_intermediates=True)
+    compare_factors(A64, g, o)
+
+
+def test_nonfinite_input_reports_numeric():
+    A = np.random.default_rng(0).standard_normal((100, 80))
+    A[5, 7] = np.nan
+    with pytest.raises(rlu.RluError) as e:
+        rlu.factor(to_dev(A), k=4, l=8, s=16, seed=1)
+    assert e.value.status == rlu.RLU_ERR_NUMERIC
+
+
+@pytest.mark.parametrize("kw", [dict(k=5, l=4, s=8), dict(k=2, l=9, s=8), dict(k=2, l=4, s=12),
+                                dict(k=2, l=70, s=128), dict(k=2, l=4, s=16384)])
+def test_invalid_arguments(kw):
+    A = to_dev(np.ones((60, 50)))
+    with pytest.raises(rlu.RluError) as e:
+        rlu.factor(A, seed=1, **kw)
+    assert e.value.status == rlu.RLU_ERR_INVALID_ARG
+
+
+def test_workspace_too_small():
+    import ctypes
+    A = to_dev(np.ones((60, 50)))
+    lib = rlu.load_library()
+    ctx = rlu.default_context()
+    mat = rlu._dense_matrix(A)
+    p = rlu._params(2, 4, 8, 1)
+    L = torch.empty(60, 4, dtype=torch.float64, device=DEV)
+    U = torch.empty(4, 50, dtype=torch.float64, device=DEV)
+    pr = torch.empty(60, dtype=torch.int32, device=DEV)
+    pc = torch.empty(50, dtype=torch.int32, device=DEV)
+    info = torch.zeros(8, dtype=torch.int32, device=DEV)
+    ws = torch.empty(1024, dtype=torch.uint8, device=DEV)
+    f = rlu.Factors(L.data_ptr(), 4, U.data_ptr(), 50, pr.data_ptr(), pc.data_ptr(), None, None, None, 0,
+                    None, None, info.data_ptr())
+    st = lib.rlu_factor(ctx.handle, ctypes.byref(mat), ctypes.byref(p), ctypes.byref(f), ws.data_ptr(), 1024,
+                        None)
+    assert st == rlu.RLU_ERR_NO_MEMORY
