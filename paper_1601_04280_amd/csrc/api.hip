@@ -23,13 +23,13 @@ rlu_status fail(rlu_status st, const char *fmt, ...) {
   return st;
 }
 rlu_status hip_fail(hipError_t e, const char *what) {
+  (void)hipGetLastError();  // a rejected launch must not surface in the caller's next HIP call
   return fail(RLU_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
 void sketch_dense_set_attrs();
-int gepp_max_blocks_per_cu(size_t lds);
 
-constexpr int kMaxL = 576;  // l x 33 doubles of the Cholesky panel must fit in LDS
+constexpr int kMaxL = 544;  // l x 34 doubles of the Cholesky panel must fit in LDS
 
 // ---------------------------------------------------------------------------
 // validation
@@ -99,13 +99,13 @@ struct FactorPlan {
   GeppPlan py, pb;
   int splits_w, splits_g;
   // offsets (bytes) into the workspace
-  size_t ctl, code, sel, twf, twp, Y, Wk, slots, Lhat, Uy, Wt, parts, Gm, Linv, Ginv, Bt, Lph,
+  size_t ctl, code, sel, twf, twp, Y, slots, Lhat, Uy, Wt, parts, Gm, Linv, Dinv, Ginv, Bt, Lph,
       Up, Lt, prec;
   size_t total;
   size_t sketch_total;
 };
 
-// control words: [0] barrier counter (Y), [1] abort flag, [2] barrier counter (B^T), [3] spare
+// control words: [1] abort flag of the cooperative launches
 constexpr int kCtlWords = 64;
 
 static void plan_sketch_part(Carver &cv, FactorPlan &fp, int64_t n, int l, int s) {
@@ -134,7 +134,6 @@ rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_pa
   plan_sketch_part(cv, *fp, n, l, p->s);
   fp->sketch_total = cv.off;
   fp->Y = cv.take((size_t)m * l * 8);
-  fp->Wk = cv.take((fp->py.multi || fp->pb.multi) ? (size_t)std::max(m, n) * l * 8 : 0);
   fp->slots = cv.take(std::max(gepp_workspace_bytes(m, l, fp->py), gepp_workspace_bytes(n, l, fp->pb)));
   fp->Lhat = cv.take((size_t)m * l * 8);
   fp->Uy = cv.take((size_t)l * l * 8);
@@ -143,6 +142,7 @@ rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_pa
                                gemm_f64_splitk_scratch(l, l, fp->splits_g)));
   fp->Gm = cv.take((size_t)l * l * 8);
   fp->Linv = cv.take((size_t)l * l * 8);
+  fp->Dinv = cv.take(chol_scratch_bytes(l));
   fp->Ginv = cv.take((size_t)l * l * 8);
   fp->Bt = cv.take((size_t)n * l * 8);
   fp->Lph = cv.take((size_t)n * l * 8);
@@ -251,8 +251,8 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   double *Lhat = at<double>(ws, fp.Lhat);
   double *Uy = out->Uy ? out->Uy : at<double>(ws, fp.Uy);
   sm.mark(RLU_STAGE_LU_Y);
-  e = launch_gepp(m, l, Y, ldy, at<double>(ws, fp.Wk), Lhat, Uy, out->perm_r, out->ipiv_r,
-                  at<void>(ws, fp.slots), ctl + 0, abort_flag, info, 0, fp.py, st);
+  e = launch_gepp(m, l, Y, ldy, Lhat, Uy, out->perm_r, out->ipiv_r, at<void>(ws, fp.slots), abort_flag, info,
+                  0, fp.py, st);
   if (e != hipSuccess) return hip_fail(e, "row-pivoted LU launch");
 
   // Step 4: W^T = A^T Lhat (n x l) and G = Lhat^T Lhat
@@ -281,7 +281,7 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     if (e != hipSuccess) return hip_fail(e, "Gram matrix");
   }
   sm.mark(RLU_STAGE_CHOL);
-  if ((e = launch_chol_inv(l, at<double>(ws, fp.Gm), at<double>(ws, fp.Linv), info, st)) != hipSuccess)
+  if ((e = launch_chol_inv(l, at<double>(ws, fp.Gm), at<double>(ws, fp.Linv), at<double>(ws, fp.Dinv), info, st)) != hipSuccess)
     return hip_fail(e, "Cholesky");
   {  // G^{-1} = Linv^T Linv
     GemmArgs g{};
@@ -311,8 +311,8 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   // Step 5: B Q = L~ U through the row-pivoted LU of B^T
   double *Lph = at<double>(ws, fp.Lph), *Up = at<double>(ws, fp.Up), *Lt = at<double>(ws, fp.Lt);
   sm.mark(RLU_STAGE_LU_B);
-  e = launch_gepp(n, l, Bt, l, at<double>(ws, fp.Wk), Lph, Up, out->perm_c, out->ipiv_c,
-                  at<void>(ws, fp.slots), ctl + 2, abort_flag, info, 1, fp.pb, st);
+  e = launch_gepp(n, l, Bt, l, Lph, Up, out->perm_c, out->ipiv_c, at<void>(ws, fp.slots), abort_flag, info, 1,
+                  fp.pb, st);
   if (e != hipSuccess) return hip_fail(e, "column-pivoted LU launch");
   sm.mark(RLU_STAGE_ASSEMBLE);
   if ((e = launch_ltilde(l, Up, Lt, st)) != hipSuccess) return hip_fail(e, "L~");
@@ -472,7 +472,6 @@ rlu_status rlu_tall_lu_workspace_size(rlu_ctx *ctx, int64_t rows, int64_t cols, 
   Carver cv;
   cv.take(kCtlWords * 4);
   cv.take(gepp_workspace_bytes(rows, (int)cols, gp));
-  cv.take(gp.multi ? (size_t)rows * cols * 8 : 0);
   *bytes = cv.off;
   return RLU_OK;
 }
@@ -494,7 +493,6 @@ rlu_status rlu_tall_lu(rlu_ctx *ctx, const double *X, int64_t rows, int64_t cols
   Carver cv;
   const size_t o_ctl = cv.take(kCtlWords * 4);
   const size_t o_slots = cv.take(gepp_workspace_bytes(rows, (int)cols, gp));
-  const size_t o_wk = cv.take(gp.multi ? (size_t)rows * cols * 8 : 0);
   hipError_t e = hipSetDevice(cx.caps.device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -502,8 +500,8 @@ rlu_status rlu_tall_lu(rlu_ctx *ctx, const double *X, int64_t rows, int64_t cols
   if ((e = launch_fill_u32(ctl, 0u, kCtlWords, s)) != hipSuccess) return hip_fail(e, "fill");
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(info), 0u, sizeof(rlu_info) / 4, s)) != hipSuccess)
     return hip_fail(e, "fill");
-  e = launch_gepp(rows, (int)cols, X, ldx, at<double>(ws, o_wk), Lhat, U, perm, ipiv, at<void>(ws, o_slots),
-                  ctl, reinterpret_cast<int32_t *>(ctl + 1), info, 0, gp, s);
+  e = launch_gepp(rows, (int)cols, X, ldx, Lhat, U, perm, ipiv, at<void>(ws, o_slots),
+                  reinterpret_cast<int32_t *>(ctl + 1), info, 0, gp, s);
   if (e != hipSuccess) return hip_fail(e, "tall LU launch");
   if ((e = launch_finalize(info, reinterpret_cast<int32_t *>(ctl + 1), s)) != hipSuccess) return hip_fail(e, "finalize");
   return RLU_OK;

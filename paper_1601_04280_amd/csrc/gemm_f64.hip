@@ -3,9 +3,10 @@
 //   W^T = A^T Lhat  (n x l, the dominant contraction, K = m),
 //   G   = Lhat^T Lhat, and the small l x l / n x l / m x l products.
 //
-// Block tile 64 (M) x 16*TN (N), K staged through LDS 16 at a time; the
-// four waves of a block each own 16 rows of the tile and TN 16x16
-// accumulators.  op(A) is A (M x K, row major, optional row gather) or A^T
+// Block tile 64 (M) x 16*TN (N), K staged through LDS 32 at a time with
+// the next tile's global loads in flight (in registers) during the MFMAs of
+// the current one; the four waves of a block each own 16 rows of the tile
+// and TN 16x16 accumulators.  op(A) is A (M x K, row major, optional row gather) or A^T
 // (A stored K x M).  A may be FP32 storage, widened exactly to FP64 on load.
 // Split-K writes per-split partials that a second kernel sums in a fixed
 // order (deterministic).
@@ -31,13 +32,22 @@ struct GemmK {
   int partial;
 };
 
-constexpr int kBM = 64, kBK = 16;
+constexpr int kBM = 64, kBK = 32;
+
+// LDS row strides (doubles) congruent to 16 mod 32, i.e. 128 bytes mod 256:
+// the four 16-lane groups of an MFMA operand read (rows k..k+3) then fall on
+// two disjoint halves of the banks, the minimum of two passes per read.
+constexpr int pad_stride(int w) { return w + ((16 - (w % 32)) + 32) % 32; }
 
 template <typename TAt, bool TRA, bool GATH, int TN>
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmK p) {
   constexpr int BN = 16 * TN;
-  __shared__ double As[kBK][kBM];
-  __shared__ double Bs[kBK][BN];
+  constexpr int AS = pad_stride(kBM);
+  constexpr int BS = pad_stride(BN);
+  constexpr int AR = (kBK * kBM) / 256;  // A elements per thread per tile
+  constexpr int BR = (kBK * BN) / 256;   // B elements per thread per tile
+  __shared__ double As[kBK * AS];
+  __shared__ double Bs[kBK * BS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t m0 = (int64_t)blockIdx.x * kBM, n0 = (int64_t)blockIdx.y * BN;
   const int64_t kb = (int64_t)blockIdx.z * p.Kc;
@@ -47,48 +57,75 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmK p) {
 #pragma unroll
   for (int t = 0; t < TN; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  for (int64_t k0 = kb; k0 < ke; k0 += kBK) {
+  TAt ra[AR];
+  double rb[BR];
+  auto load = [&](int64_t k0) {
 #pragma unroll
-    for (int r = 0; r < (kBK * kBM) / 256; ++r) {
+    for (int r = 0; r < AR; ++r) {
       const int e = tid + 256 * r;
-      if (TRA) {
-        const int k = e >> 6, m = e & 63;
-        const int64_t gk = k0 + k, gm = m0 + m;
-        As[k][m] = (gk < ke && gm < p.M) ? (double)A[gk * p.lda + gm] : 0.0;
-      } else {
-        const int m = e >> 4, k = e & 15;
-        const int64_t gk = k0 + k, gm = m0 + m;
-        double v = 0.0;
-        if (gk < ke && gm < p.M) {
-          const int64_t row = GATH ? (int64_t)p.gather[gm] : gm;
-          v = (double)A[row * p.lda + gk];
-        }
-        As[k][m] = v;
+      int k, m;
+      if (TRA) { k = e >> 6; m = e & 63; } else { m = e >> 5; k = e & 31; }
+      const int64_t gk = k0 + k, gm = m0 + m;
+      TAt v = (TAt)0;
+      if (gk < ke && gm < p.M) {
+        if (TRA) v = A[gk * p.lda + gm];
+        else v = A[(GATH ? (int64_t)p.gather[gm] : gm) * p.lda + gk];
       }
+      ra[r] = v;
     }
-    for (int e = tid; e < kBK * BN; e += 256) {
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      const int e = tid + 256 * r;
       const int k = e / BN, n = e - k * BN;
       const int64_t gk = k0 + k, gn = n0 + n;
-      Bs[k][n] = (gk < ke && gn < p.N) ? p.B[gk * p.ldb + gn] : 0.0;
+      rb[r] = (gk < ke && gn < p.N) ? p.B[gk * p.ldb + gn] : 0.0;
     }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int r = 0; r < AR; ++r) {
+      const int e = tid + 256 * r;
+      int k, m;
+      if (TRA) { k = e >> 6; m = e & 63; } else { m = e >> 5; k = e & 31; }
+      As[k * AS + m] = (double)ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+      const int e = tid + 256 * r;
+      const int k = e / BN, n = e - k * BN;
+      Bs[k * BS + n] = rb[r];
+    }
+  };
+
+  if (kb < ke) {
+    load(kb);
+    store();
     __syncthreads();
+  }
+  for (int64_t k0 = kb; k0 < ke; k0 += kBK) {
+    const bool more = k0 + kBK < ke;
+    if (more) load(k0 + kBK);  // in flight during the MFMAs below
 #pragma unroll
     for (int kk = 0; kk < kBK / 4; ++kk) {
-      const double a = As[kk * 4 + (lane >> 4)][wave * 16 + (lane & 15)];
+      const double a = As[(kk * 4 + (lane >> 4)) * AS + wave * 16 + (lane & 15)];
 #pragma unroll
       for (int t = 0; t < TN; ++t) {
-        const double b = Bs[kk * 4 + (lane >> 4)][t * 16 + (lane & 15)];
+        const double b = Bs[(kk * 4 + (lane >> 4)) * BS + t * 16 + (lane & 15)];
         acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
       }
     }
     __syncthreads();
+    if (more) {
+      store();
+      __syncthreads();
+    }
   }
 
 #pragma unroll
   for (int t = 0; t < TN; ++t) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int64_t m = m0 + wave * 16 + 4 * (lane >> 4) + v;
+      const int64_t m = m0 + wave * 16 + (lane >> 4) + 4 * v;  // D row = lane/16 + 4 v
       const int64_t n = n0 + t * 16 + (lane & 15);
       if (m < p.M && n < p.N) {
         if (p.partial) {
@@ -174,7 +211,7 @@ hipError_t gemm_f64(const GemmArgs &g, hipStream_t st) {
 int choose_splits(int64_t M, int64_t N, int64_t K, int num_cu) {
   const int tn = pick_tn(N);
   const int64_t tiles = ceil_div(M, kBM) * ceil_div(N, 16 * tn);
-  int64_t s = ceil_div(2 * (int64_t)num_cu, tiles);
+  int64_t s = ceil_div((int64_t)num_cu, tiles);  // one block per CU (register bound)
   s = std::min<int64_t>(s, std::max<int64_t>(1, K / 256));
   s = std::min<int64_t>(s, 64);
   return (int)std::max<int64_t>(1, s);

@@ -37,47 +37,73 @@ __device__ inline uint32_t code_bucket(uint32_t c) { return c & 0xFFFFu; }
 __device__ inline double code_apply(uint32_t c, double v) { return (c >> 31) ? -v : v; }
 
 // ---------------------------------------------------------------------------
-// Device-wide barrier for cooperative (co-resident) launches.
-//
-// Monotonic counter: barrier number b completes when the counter reaches
-// b * nblocks.  Every wave issues an agent-scope release fence before the
-// block barrier (the block barrier alone does not wait for other waves'
-// stores to leave the CU, and L2s of different XCDs are not coherent), so
-// that everything the block wrote is visible device-wide before thread 0
-// arrives.  Waiting is bounded: after `timeout_ticks` of the 100 MHz
-// real-time counter, or when another block has raised the abort flag, the
-// wait fails and the caller must leave the kernel.
+// Tagged words: 32 bits of data and a 32-bit tag in one 64-bit word, written
+// and read with agent-scope atomic stores / loads.  A reader that sees the
+// expected tag also sees the data that came with it, so blocks exchange
+// values without read-modify-write atomics and without cache-wide fences
+// (a counter that every block increments serialises at the memory side;
+// one word per block, polled by all, does not).  Buffers are zeroed before
+// each launch and tags start at 1.
 // ---------------------------------------------------------------------------
-struct GridSync {
-  uint32_t *counter;
+__device__ inline void tw_put(uint64_t *w, uint32_t data, uint32_t tag) {
+  __hip_atomic_store(w, (uint64_t)data | ((uint64_t)tag << 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint64_t tw_get(const uint64_t *w) {
+  return __hip_atomic_load(const_cast<uint64_t *>(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint32_t tw_tag(uint64_t v) { return (uint32_t)(v >> 32); }
+__device__ inline uint32_t tw_data(uint64_t v) { return (uint32_t)v; }
+__device__ inline void tw_put_f64(uint64_t *w, double x, uint32_t tag) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  tw_put(w, (uint32_t)b, tag);
+  tw_put(w + 1, (uint32_t)(b >> 32), tag);
+}
+__device__ inline double tw_f64(uint64_t lo, uint64_t hi) {
+  return __longlong_as_double((long long)(((uint64_t)tw_data(hi) << 32) | tw_data(lo)));
+}
+
+// Bounded poll helper: true while the deadline has not passed and no block
+// raised the abort flag; raises the flag on time-out.
+__device__ inline bool poll_ok(uint64_t t0, uint64_t timeout_ticks, int32_t *abort_flag) {
+  if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+  if (__builtin_amdgcn_s_memrealtime() - t0 > timeout_ticks) {
+    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return false;
+  }
+  return true;
+}
+
+// Flag barrier over the blocks of a cooperative launch: every block stores
+// its own tag (128 bytes apart), every block polls all of them.  Data
+// written before the barrier with plain stores is published by the
+// agent-scope release fence of every wave and picked up by the acquire
+// fence after the wait.
+struct FlagBar {
+  uint64_t *flags;     // nblocks x 16 words, zeroed before the launch
   int32_t *abort_flag;
-  uint32_t nblocks;
+  int nblocks;
   uint64_t timeout_ticks;
 };
 
-__device__ inline void grid_arrive(const GridSync &gs) {
+__device__ inline void fbar_arrive(const FlagBar &fb, uint32_t tag) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(gs.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) tw_put(fb.flags + (size_t)blockIdx.x * 16, 0u, tag);
 }
 
-// Returns true when barrier `number` (1-based) completed for every block.
-__device__ inline bool grid_wait(const GridSync &gs, uint32_t number, int *lds_flag) {
-  if (threadIdx.x == 0) {
-    const uint32_t target = number * gs.nblocks;
+__device__ inline bool fbar_wait(const FlagBar &fb, uint32_t tag, int *lds_flag) {
+  if (threadIdx.x < 64) {
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     int ok = 1;
-    uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-    while (__hip_atomic_load(gs.counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(gs.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = 0; break; }
-      if (__builtin_amdgcn_s_memrealtime() - t0 > gs.timeout_ticks) {
-        __hip_atomic_store(gs.abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = 0;
-        break;
-      }
+    for (;;) {
+      int all = 1;
+      for (int g = threadIdx.x; g < fb.nblocks; g += 64) all &= (tw_tag(tw_get(fb.flags + (size_t)g * 16)) >= tag);
+      if (__all(all)) break;
+      if (!poll_ok(t0, fb.timeout_ticks, fb.abort_flag)) { ok = 0; break; }
       __builtin_amdgcn_s_sleep(1);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    *lds_flag = ok;
+    if (threadIdx.x == 0) *lds_flag = ok;
   }
   __syncthreads();
   return *lds_flag != 0;

@@ -60,13 +60,13 @@ struct DevCaps {
 };
 bool plan_gepp(int64_t rows, int cols, const DevCaps &caps, GeppPlan *plan, std::string *why);
 size_t gepp_workspace_bytes(int64_t rows, int cols, const GeppPlan &plan);
-// X: rows x cols (ldx); work: rows x cols scratch when plan.multi; slots and
-// control words come from `ws` (gepp_workspace_bytes); ctl points at two
-// zeroed words (barrier counter, abort flag).
-hipError_t launch_gepp(int64_t rows, int cols, const double *X, int64_t ldx, double *work,
-                       double *Lhat, double *U, int32_t *perm, int32_t *ipiv, void *ws,
-                       uint32_t *bar_counter, int32_t *abort_flag, rlu_info *info, int which,
-                       const GeppPlan &plan, hipStream_t st);
+// X: rows x cols (ldx), left unchanged.  The exchange slots, positions and
+// (for more than one panel) a working copy of X live in `ws`
+// (gepp_workspace_bytes); abort_flag is a zeroed word shared by the launches
+// of one call.
+hipError_t launch_gepp(int64_t rows, int cols, const double *X, int64_t ldx, double *Lhat, double *U,
+                       int32_t *perm, int32_t *ipiv, void *ws, int32_t *abort_flag, rlu_info *info,
+                       int which, const GeppPlan &plan, hipStream_t st);
 
 // ---- FP64 GEMM on MFMA ------------------------------------------------------------
 // C (M x N, ldc) = alpha * op(A) * op(B) + beta * C, or split-K partials.
@@ -89,7 +89,9 @@ int choose_splits(int64_t M, int64_t N, int64_t K, int num_cu);
 // ---- small dense FP64 pieces ---------------------------------------------------------
 // In place: G (l x l, ld l, SPD) -> Linv = inverse of the Cholesky factor
 // (G = L L^T), written to Linv (l x l, lower, zeros above).
-hipError_t launch_chol_inv(int l, double *G, double *Linv, rlu_info *info, hipStream_t st);
+hipError_t launch_chol_inv(int l, double *G, double *Linv, double *dinv_scratch, rlu_info *info,
+                           hipStream_t st);
+size_t chol_scratch_bytes(int l);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t st);
 hipError_t launch_ltilde(int l, const double *Up, double *Lt, hipStream_t st);
 hipError_t launch_assemble_u(int l, int64_t n, const double *Up, const double *Lphat,
