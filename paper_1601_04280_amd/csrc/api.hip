@@ -28,6 +28,7 @@ rlu_status hip_fail(hipError_t e, const char *what) {
 }
 
 void sketch_dense_set_attrs();
+void sketch_csr_set_attrs();
 
 constexpr int kMaxL = 544;  // l x 34 doubles of the Cholesky panel must fit in LDS
 
@@ -99,7 +100,7 @@ struct FactorPlan {
   GeppPlan py, pb;
   int splits_w, splits_g;
   // offsets (bytes) into the workspace
-  size_t ctl, code, sel, twf, twp, Y, slots, Lhat, Uy, Wt, parts, Gm, Linv, Dinv, Ginv, Bt, Lph,
+  size_t ctl, code, sel, twf, twp, Y, slots, csc, Lhat, Uy, Wt, parts, Gm, Linv, Dinv, Ginv, Bt, Lph,
       Up, Lt, prec;
   size_t total;
   size_t sketch_total;
@@ -148,6 +149,7 @@ rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_pa
   fp->Lph = cv.take((size_t)n * l * 8);
   fp->Up = cv.take((size_t)l * l * 8);
   fp->Lt = cv.take((size_t)l * l * 8);
+  fp->csc = cv.take(A->layout == RLU_CSR ? csc_scratch_bytes(n, A->nnz) : 0);
   fp->prec = cv.take(p->precision == RLU_PREC_F64 ? 0 : precision_scratch_bytes(m, n, l, p->precision, cx.caps.num_cu));
   fp->total = cv.off;
   return RLU_OK;
@@ -167,7 +169,6 @@ static rlu_status run_params(const FactorPlan &fp, const rlu_params *p, void *ws
   return e == hipSuccess ? RLU_OK : hip_fail(e, "parameter kernels");
 }
 
-hipError_t launch_csr_check(const rlu_matrix *A, int validate_cols, rlu_info *info, hipStream_t st);
 
 static rlu_status run_sketch(const rlu_ctx_impl &cx, const FactorPlan &fp, const rlu_matrix *A,
                              const rlu_params *p, double *Y, int64_t ldy, void *ws, rlu_info *info,
@@ -182,16 +183,14 @@ static rlu_status run_sketch(const rlu_ctx_impl &cx, const FactorPlan &fp, const
       e = launch_csr_check(A, (p->flags & RLU_FLAG_VALIDATE) != 0, info, st);
       if (e != hipSuccess) return hip_fail(e, "CSR check");
     }
-    e = launch_sketch_csr(A->m, A->n, A->row_ptr, A->col_idx, (const double *)A->values, p->s, p->l,
+    e = launch_sketch_csr(A->m, A->n, A->row_ptr, A->col_idx, (const double *)A->values, A->nnz, p->s, p->l,
                           at<uint32_t>(ws, fp.code), at<int32_t>(ws, fp.sel), at<double2>(ws, fp.twf),
-                          at<double2>(ws, fp.twp), Y, ldy, info ? &info->bad_index : nullptr,
+                          at<double2>(ws, fp.twp), Y, ldy, info ? &info->bad_index : at<int32_t>(ws, fp.ctl) + 2,
                           cx.caps.num_cu, st);
   }
   return e == hipSuccess ? RLU_OK : hip_fail(e, "sketch kernel");
 }
 
-hipError_t contraction_csr(int64_t m, int64_t n, int l, const int32_t *row_ptr, const int32_t *col,
-                           const double *val, const double *Lhat, double *Wt, hipStream_t st);
 rlu_status run_precision_contraction(const rlu_ctx_impl &cx, const FactorPlan &fp, const rlu_matrix *A,
                                      const rlu_params *p, void *ws, hipStream_t st);
 
@@ -259,7 +258,8 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   double *Wt = at<double>(ws, fp.Wt);
   sm.mark(RLU_STAGE_CONTRACT);
   if (A->layout == RLU_CSR) {
-    e = contraction_csr(m, n, l, A->row_ptr, A->col_idx, (const double *)A->values, Lhat, Wt, st);
+    e = contraction_csr(m, n, l, A->row_ptr, A->col_idx, (const double *)A->values, A->nnz, Lhat, Wt,
+                        at<void>(ws, fp.csc), cx.caps.num_cu, st);
     if (e != hipSuccess) return hip_fail(e, "sparse contraction");
   } else if (p->precision == RLU_PREC_F64) {
     GemmArgs g{};
@@ -365,6 +365,7 @@ rlu_status rlu_create(int device, rlu_ctx **ctx) {
   c->caps.num_cu = prop.multiProcessorCount;
   c->caps.max_lds = prop.sharedMemPerBlockOptin ? prop.sharedMemPerBlockOptin : prop.sharedMemPerBlock;
   sketch_dense_set_attrs();
+  sketch_csr_set_attrs();
   *ctx = reinterpret_cast<rlu_ctx *>(c);
   return RLU_OK;
 }

@@ -4,16 +4,6 @@
 
 namespace rlu {
 
-hipError_t launch_csr_check(const rlu_matrix *, int, rlu_info *, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_sketch_csr(int64_t, int64_t, const int32_t *, const int32_t *, const double *, int, int,
-                             const uint32_t *, const int32_t *, const double2 *, const double2 *, double *,
-                             int64_t, int32_t *, int, hipStream_t) {
-  return hipErrorNotSupported;
-}
-hipError_t contraction_csr(int64_t, int64_t, int, const int32_t *, const int32_t *, const double *,
-                           const double *, double *, hipStream_t) {
-  return hipErrorNotSupported;
-}
 struct FactorPlan;
 size_t precision_scratch_bytes(int64_t, int64_t, int, int, int) { return 0; }
 rlu_status run_precision_contraction(const rlu_ctx_impl &, const FactorPlan &, const rlu_matrix *,

@@ -18,7 +18,7 @@ inline int ilog2_exact(int64_t v) {
   while ((int64_t(1) << b) < v) ++b;
   return b;
 }
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 constexpr int kMaxS = 8192;            // LDS-resident transform: 16 s bytes per block
@@ -39,10 +39,15 @@ hipError_t launch_sketch_dense(int64_t m, int64_t n, const void *A, int dtype, i
                                const double2 *twf, const double2 *twp, double *Y, int64_t ldy,
                                int num_cu, hipStream_t st);
 hipError_t launch_sketch_csr(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t *col,
-                             const double *val, int s, int l, const uint32_t *code,
-                             const int32_t *sel, const double2 *twf, const double2 *twp,
-                             double *Y, int64_t ldy, int32_t *bad_index, int num_cu,
-                             hipStream_t st);
+                             const double *val, int64_t nnz, int s, int l, const uint32_t *code,
+                             const int32_t *sel, const double2 *twf, const double2 *twp, double *Y,
+                             int64_t ldy, int32_t *bad_index, int num_cu, hipStream_t st);
+hipError_t launch_csr_check(const rlu_matrix *A, int validate_rows, rlu_info *info, hipStream_t st);
+size_t csc_scratch_bytes(int64_t n, int64_t nnz);
+// W^T (n x l) = A^T Lhat for CSR A, through a CSC copy built in `scratch`
+hipError_t contraction_csr(int64_t m, int64_t n, int l, const int32_t *row_ptr, const int32_t *col,
+                           const double *val, int64_t nnz, const double *Lhat, double *Wt, void *scratch,
+                           int num_cu, hipStream_t st);
 
 // ---- tall pivoted LU (cooperative) ---------------------------------------------
 struct GeppPlan {
