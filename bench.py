@@ -3,29 +3,42 @@
 
 One step = one whole decomposition (Algorithm 1 with the exact least-squares
 product): sketch, row-pivoted LU of the sketch, least-squares product,
-column-pivoted LU, L = L_y L~, on a synthetic dense 16384 x 8192 FP64 matrix
-with singular values i^-2 (k = 200, l = 210, s = 2048), resident in HBM.
+column-pivoted LU, L = L_y L~.  The headline workload is a synthetic dense
+16384 x 8192 FP64 matrix with singular values i^-2 (k = 200, l = 210,
+s = 2048), resident in HBM.
 
-Prints one JSON line.  `value` is decompositions per second; `roofline`
-describes the stage whose kernel dominates the step among the
-bandwidth/MFMA-bound ones, timed with HIP events on the library's stream
-inside the timed region; `cpu_baseline` times the oracle on the host.
+Prints one JSON line.  `value` is decompositions per second of the headline
+workload; `roofline` describes the stage whose kernels dominate the step
+among the bandwidth/MFMA-bound ones, timed with HIP events on the library's
+stream inside the timed region; `cpu_baseline` times the oracle on the host.
+Unless --no-extras, the line also carries
+  `forms`: the 32768 x 16384 FP32-stored matrix with sigma_i = exp(-i/100)
+           (k = 500, l = 520, s = 4096) decomposed with the contraction in
+           FP64, FP32 and BF16 + one refinement step, side by side, each with
+           its relative residual ||LU - PAQ||_F / ||A||_F;
+  `csr`:   the 200000 x 100000 CSR matrix at 0.1% density with a rank-50
+           plant (k = 100, l = 110, s = 4096).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
 import time
 
+HERE = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 
 WORKLOADS = {
-    "dense_16384x8192_invsq": dict(m=16384, n=8192, k=200, l=210, s=2048),
-    "dense_1024x512_geometric": dict(m=1024, n=512, k=20, l=30, s=256),
+    "dense_16384x8192_invsq": dict(m=16384, n=8192, k=200, l=210, s=2048, precision="f64"),
+    "dense_1024x512_geometric": dict(m=1024, n=512, k=20, l=30, s=256, precision="f64"),
+    "dense_32768x16384_exp_fp32": dict(m=32768, n=16384, k=500, l=520, s=4096, precision="bf16"),
+    "csr_200000x100000_planted": dict(m=200000, n=100000, k=100, l=110, s=4096, precision="f64"),
 }
+SEED = 2
 
 
 def parse():
@@ -34,24 +47,107 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="dense_16384x8192_invsq", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", choices=["f64", "f32", "bf16"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget-s", type=float, default=30.0)
+    ap.add_argument("--no-extras", action="store_true")
     return ap.parse_args()
 
 
 def make_input(name, device):
-    import numpy as np
-    import synth
-    w = WORKLOADS[name]
-    if name == "dense_16384x8192_invsq":
-        return synth.invsq_dense_torch(w["m"], w["n"], device=device)
+    """Device-resident input: a tensor (dense) or (row_ptr, col, val, m, n)."""
     import torch
+    import synth
+    if name == "dense_16384x8192_invsq":
+        return synth.invsq_dense_torch(16384, 8192, device=device)
+    if name == "dense_32768x16384_exp_fp32":
+        return synth.exp_dense_fp32_torch(32768, 16384, device=device)
+    if name == "csr_200000x100000_planted":
+        rp, col, val = synth.planted_csr()
+        return (torch.from_numpy(rp).to(device), torch.from_numpy(col).to(device),
+                torch.from_numpy(val).to(device), 200000, 100000)
     return torch.from_numpy(synth.small_dense()).to(device)
 
 
-def cpu_baseline(A_dev, w, seed, budget_s):
+def input_bytes(A):
+    if isinstance(A, tuple):
+        rp, col, val, m, n = A
+        return rp.numel() * 4 + col.numel() * 4 + val.numel() * 8
+    return A.numel() * A.element_size()
+
+
+def run(rlu, A, w, precision, steps, warmup, ctx):
+    """Warm-up, then `steps` timed decompositions; returns timings and the output."""
+    import torch
+    kw = dict(k=w["k"], l=w["l"], s=w["s"], seed=SEED, ctx=ctx, precision=precision)
+    if isinstance(A, tuple):
+        kw["csr"] = A
+        A = None
+    out = rlu.factor(A, **kw)                                   # allocates outputs, checks status
+    for _ in range(warmup):
+        rlu.factor(A, out=out, check=False, **kw)
+    torch.cuda.synchronize()
+    ctx.stage_times()                                           # clear
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rlu.factor(A, out=out, check=False, flags=rlu.RLU_FLAG_TIMING, **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages, calls = ctx.stage_times()
+    info = out.info_dict()
+    if info["status"] != 0:
+        raise SystemExit(f"device-side failure during the timed steps: {info}")
+    per = {k: v / max(calls, 1) for k, v in stages.items()}
+    return (t1 - t0) * 1e3 / steps, per, out
+
+
+def rel_residual(A, out):
+    """||LU - PAQ||_F / ||A||_F in FP64 on the device (a check, outside the timing)."""
+    import torch
+    A64 = A.double()
+    pr, pc = out.perm_r.long(), out.perm_c.long()
+    R = out.L @ out.U
+    R -= A64[pr][:, pc]
+    r = (torch.linalg.norm(R) / torch.linalg.norm(A64)).item()
+    del R, A64
+    torch.cuda.empty_cache()
+    return r
+
+
+def sketch_rate(A, w, per):
+    byts = input_bytes(A) + 8 * w["m"] * w["l"]
+    gbs = byts / (per["sketch"] * 1e-3) / 1e9
+    return {"achieved": round(gbs, 1), "unit": "GB/s", "peak": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "bytes": byts}
+
+
+def contract_rate(w, per, precision):
+    flops = 2.0 * w["m"] * w["n"] * w["l"] * (1 if precision != "bf16" else 5)  # BF16: W0, 3 split products, dW
+    ms = per["contract"] + (per["solve"] if precision == "bf16" else 0.0)
+    tfs = flops / (ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[precision]
+    return {"achieved": round(tfs, 3), "unit": "TFLOP/s", "peak": peak, "frac": round(tfs / peak, 4),
+            "flops": flops}
+
+
+def measured_traffic(kernel_key):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the kernel source as it is now (else None)."""
+    path = os.path.join(HERE, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)[kernel_key]
+        src = os.path.join(HERE, rec["source"])
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        if sha != rec["source_sha256"]:
+            return None
+        return rec["bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(A_dev, w):
     """The oracle as it stands, on the host, on one full decomposition."""
-    import numpy as np
     from oracle import rlu as R
     try:
         from threadpoolctl import threadpool_info
@@ -60,10 +156,51 @@ def cpu_baseline(A_dev, w, seed, budget_s):
         threads = os.cpu_count() or 1
     A = A_dev.cpu().numpy()
     t0 = time.perf_counter()
-    R.rlu(A, R.Params(w["k"], w["l"], w["s"], seed))
+    R.rlu(A, R.Params(w["k"], w["l"], w["s"], SEED))
     dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "decomps/s", "cores": int(threads), "kind": "oracle",
+    return {"value": round(1.0 / dt, 5), "unit": "decomps/s", "cores": int(threads), "kind": "oracle",
             "sample": f"1 full decomposition of the same {w['m']}x{w['n']} matrix ({dt:.1f} s)"}
+
+
+def forms_block(rlu, ctx, dev):
+    import torch
+    name = "dense_32768x16384_exp_fp32"
+    w = WORKLOADS[name]
+    A = make_input(name, dev)
+    torch.cuda.synchronize()
+    res = {"workload": name, "m": w["m"], "n": w["n"], "k": w["k"], "l": w["l"], "s": w["s"], "storage": "float32"}
+    for prec in ("f64", "f32", "bf16"):
+        ms, per, out = run(rlu, A, w, prec, steps=5, warmup=1, ctx=ctx)
+        res[prec] = {"ms_per_step": round(ms, 3), "decomps_per_s": round(1e3 / ms, 3),
+                     "rel_residual": rel_residual(A, out),
+                     "contract": contract_rate(w, per, prec),
+                     "stages_ms": {k: round(v, 4) for k, v in per.items()}}
+        del out
+        print(f"# forms {prec}: {ms:.2f} ms/step, residual {res[prec]['rel_residual']:.6e}", file=sys.stderr,
+              flush=True)
+    r64 = res["f64"]["rel_residual"]
+    for prec in ("f32", "bf16"):
+        res[prec]["residual_rel_diff_vs_f64"] = abs(res[prec]["rel_residual"] - r64) / r64
+        res[prec]["speedup_vs_f64"] = round(res["f64"]["ms_per_step"] / res[prec]["ms_per_step"], 3)
+    res["sketch"] = sketch_rate(A, w, per)
+    del A
+    torch.cuda.empty_cache()
+    return res
+
+
+def csr_block(rlu, ctx, dev):
+    import torch
+    name = "csr_200000x100000_planted"
+    w = WORKLOADS[name]
+    A = make_input(name, dev)
+    ms, per, out = run(rlu, A, w, "f64", steps=10, warmup=2, ctx=ctx)
+    res = {"workload": name, "m": w["m"], "n": w["n"], "nnz": int(A[2].numel()), "k": w["k"], "l": w["l"],
+           "s": w["s"], "ms_per_step": round(ms, 3), "decomps_per_s": round(1e3 / ms, 3),
+           "sketch": sketch_rate(A, w, per), "stages_ms": {k: round(v, 4) for k, v in per.items()}}
+    print(f"# csr: {ms:.2f} ms/step", file=sys.stderr, flush=True)
+    del A, out
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -77,41 +214,33 @@ def main():
 
     dev = "cuda:0"
     w = WORKLOADS[args.workload]
-    seed = 2
+    precision = args.precision or w["precision"]
+    ctx = rlu.Context(0)
     A = make_input(args.workload, dev)
     torch.cuda.synchronize()
-    ctx = rlu.Context(0)
-    out = rlu.factor(A, k=w["k"], l=w["l"], s=w["s"], seed=seed, ctx=ctx)      # allocates outputs, checks
-    for _ in range(args.warmup):
-        rlu.factor(A, k=w["k"], l=w["l"], s=w["s"], seed=seed, ctx=ctx, out=out, check=False)
-    torch.cuda.synchronize()
-    ctx.stage_times()                                                          # clear
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        rlu.factor(A, k=w["k"], l=w["l"], s=w["s"], seed=seed, ctx=ctx, out=out, check=False,
-                   flags=rlu.RLU_FLAG_TIMING)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    stages, calls = ctx.stage_times()
-    info = out.info_dict()
-    if info["status"] != 0:
-        raise SystemExit(f"device-side failure during the timed steps: {info}")
+    ms_step, per, out = run(rlu, A, w, precision, args.steps, args.warmup, ctx)
+    print(f"# {args.workload} {precision}: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
 
-    m, n, l = w["m"], w["n"], w["l"]
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    per = {k: v / max(calls, 1) for k, v in stages.items()}
-    sketch_bytes = m * n * A.element_size() + 8 * m * l
-    sketch_gbs = sketch_bytes / (per["sketch"] * 1e-3) / 1e9
-    contract_flops = 2.0 * m * n * l
-    contract_tfs = contract_flops / (per["contract"] * 1e-3) / 1e12
-    if per["contract"] >= per["sketch"]:
-        roof = {"bound": "mfma", "kernel": "contract (W^T = A^T Lhat, FP64 MFMA)",
-                "achieved": round(contract_tfs, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(contract_tfs / FP64_PEAK_TFLOPS, 4), "traffic": None}
+    sk = sketch_rate(A, w, per)
+    is_csr = isinstance(A, tuple)
+    if is_csr:
+        ct = None
+        roof_contract = False
     else:
-        roof = {"bound": "hbm", "kernel": "sketch (fused SEM + SRFT)", "achieved": round(sketch_gbs, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(sketch_gbs / HBM_PEAK_GBS, 4),
-                "traffic": None}
+        ct = contract_rate(w, per, precision)
+        roof_contract = per["contract"] >= per["sketch"]
+    if roof_contract:
+        key = f"contract_{precision}_{args.workload}"
+        traffic = measured_traffic(key)
+        roof = {"bound": "mfma", "kernel": f"contract stage ({precision} MFMA GEMM W^T = A^T Lhat)",
+                "achieved": ct["achieved"], "peak": ct["peak"], "unit": "TFLOP/s", "frac": ct["frac"],
+                "traffic": traffic}
+    else:
+        key = f"sketch_{args.workload}"
+        traffic = measured_traffic(key)
+        roof = {"bound": "hbm", "kernel": "sketch (SEM + SRFT)", "achieved": sk["achieved"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": sk["frac"], "traffic": traffic}
+    storage = "csr_f64" if is_csr else str(A.dtype).replace("torch.", "")
     line = {
         "metric": "LU decomps/sec at fixed rel. error; sketch GB/s vs HBM peak; p99 latency",
         "value": round(1e3 / ms_step, 3),
@@ -123,19 +252,24 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": precision,
         "data": "synthetic",
-        "config": {"workload": args.workload, "m": m, "n": n, "k": w["k"], "l": l, "s": w["s"],
-                   "storage": str(A.dtype).replace("torch.", ""), "precision": "f64"},
+        "config": {"workload": args.workload, "m": w["m"], "n": w["n"], "k": w["k"], "l": w["l"], "s": w["s"],
+                   "storage": storage, "precision": precision},
         "roofline": roof,
-        "sketch": {"achieved": round(sketch_gbs, 1), "unit": "GB/s", "peak": HBM_PEAK_GBS,
-                   "frac": round(sketch_gbs / HBM_PEAK_GBS, 4), "bytes": sketch_bytes},
-        "contract": {"achieved": round(contract_tfs, 3), "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS,
-                     "frac": round(contract_tfs / FP64_PEAK_TFLOPS, 4), "flops": contract_flops},
+        "sketch": sk,
         "stages_ms": {k: round(v, 4) for k, v in per.items()},
     }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(A, w, seed, args.cpu_budget_s)
+    if ct is not None:
+        line["contract"] = ct
+    del out
+    if not args.no_cpu_baseline and not is_csr:
+        line["cpu_baseline"] = cpu_baseline(A, w)
+    del A
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        line["forms"] = forms_block(rlu, ctx, dev)
+        line["csr"] = csr_block(rlu, ctx, dev)
     print(json.dumps(line), flush=True)
 
 

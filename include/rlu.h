@@ -80,10 +80,12 @@ typedef enum { RLU_F64 = 0, RLU_F32 = 1 } rlu_dtype; /* storage type of A's valu
 
 /* Arithmetic of the least-squares contraction W = L^T A (step 4 above).
  * Pivot searches, the Gram matrix, its Cholesky factor and the l x l solves
- * are FP64 in every form. */
+ * are FP64 in every form.  The reduced forms apply to dense A only.
+ * BF16_REFINED: W0 = bf16(L)^T bf16(A), X0 = G^-1 W0, R = A - L X0 (L X0 from
+ * hi/lo BF16 splits, good to ~2^-16), B = X0 + G^-1 bf16(L)^T bf16(R). */
 typedef enum {
   RLU_PREC_F64 = 0,          /* FP64 MFMA                                           */
-  RLU_PREC_F32 = 1,          /* FP32 operands, FP32 accumulation, one refinement    */
+  RLU_PREC_F32 = 1,          /* FP32 operands and accumulation, single pass         */
   RLU_PREC_BF16_REFINED = 2  /* BF16 operands, FP32 accumulation, one refinement    */
 } rlu_precision;
 

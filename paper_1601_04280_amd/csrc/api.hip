@@ -64,6 +64,8 @@ rlu_status validate_params(const rlu_matrix *A, const rlu_params *p) {
   if (p->k < 1 || p->k > p->l) return fail(RLU_ERR_INVALID_ARG, "need 1 <= k <= l (k=%d l=%d)", p->k, p->l);
   if (A) {
     if (p->l > A->m || p->l > A->n) return fail(RLU_ERR_INVALID_ARG, "need l <= min(m, n) (l=%d m=%lld n=%lld)", p->l, (long long)A->m, (long long)A->n);
+    if (A->layout == RLU_CSR && p->precision != RLU_PREC_F64)
+      return fail(RLU_ERR_INVALID_ARG, "the reduced-precision forms apply to dense A only");
   }
   if (p->l > kMaxL) return fail(RLU_ERR_INVALID_ARG, "l (%d) exceeds the supported maximum %d", p->l, kMaxL);
   if (p->precision < RLU_PREC_F64 || p->precision > RLU_PREC_BF16_REFINED) return fail(RLU_ERR_INVALID_ARG, "unknown precision %d", p->precision);
@@ -99,6 +101,7 @@ struct FactorPlan {
   int l, s;
   GeppPlan py, pb;
   int splits_w, splits_g;
+  PrecPlan pp;
   // offsets (bytes) into the workspace
   size_t ctl, code, sel, twf, twp, Y, slots, csc, Lhat, Uy, Wt, parts, Gm, Linv, Dinv, Ginv, Bt, Lph,
       Up, Lt, prec;
@@ -116,8 +119,6 @@ static void plan_sketch_part(Carver &cv, FactorPlan &fp, int64_t n, int l, int s
   fp.twf = cv.take((size_t)std::max(1, s / 2) * 16);
   fp.twp = cv.take((size_t)std::max(1, s / 2) * 16);
 }
-
-size_t precision_scratch_bytes(int64_t m, int64_t n, int l, int precision, int num_cu);
 
 rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_params *p, FactorPlan *fp) {
   std::string why;
@@ -150,7 +151,11 @@ rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_pa
   fp->Up = cv.take((size_t)l * l * 8);
   fp->Lt = cv.take((size_t)l * l * 8);
   fp->csc = cv.take(A->layout == RLU_CSR ? csc_scratch_bytes(n, A->nnz) : 0);
-  fp->prec = cv.take(p->precision == RLU_PREC_F64 ? 0 : precision_scratch_bytes(m, n, l, p->precision, cx.caps.num_cu));
+  fp->pp = PrecPlan{};
+  if (A->layout == RLU_DENSE_ROW_MAJOR && p->precision != RLU_PREC_F64 &&
+      !plan_precision(m, n, l, p->precision, cx.caps.num_cu, &fp->pp))
+    return fail(RLU_ERR_INVALID_ARG, "unknown precision %d", p->precision);
+  fp->prec = cv.take(fp->pp.total);
   fp->total = cv.off;
   return RLU_OK;
 }
@@ -190,9 +195,6 @@ static rlu_status run_sketch(const rlu_ctx_impl &cx, const FactorPlan &fp, const
   }
   return e == hipSuccess ? RLU_OK : hip_fail(e, "sketch kernel");
 }
-
-rlu_status run_precision_contraction(const rlu_ctx_impl &cx, const FactorPlan &fp, const rlu_matrix *A,
-                                     const rlu_params *p, void *ws, hipStream_t st);
 
 // Stage-boundary events of one timed call (no-ops when timing is off).
 struct StageMarks {
@@ -269,6 +271,9 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     g.C = Wt; g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
     e = gemm_f64_splitk(g, fp.splits_w, at<double>(ws, fp.parts), st);
     if (e != hipSuccess) return hip_fail(e, "contraction");
+  } else {
+    e = precision_contract(fp.pp, A, Lhat, l, Wt, at<double>(ws, fp.parts), fp.splits_w, at<void>(ws, fp.prec), st);
+    if (e != hipSuccess) return hip_fail(e, "reduced-precision contraction");
   }
   sm.mark(RLU_STAGE_GRAM);
   {
@@ -292,9 +297,10 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     if ((e = gemm_f64(g, st)) != hipSuccess) return hip_fail(e, "inverse Gram");
   }
   sm.mark(RLU_STAGE_SOLVE);
-  if (A->layout == RLU_DENSE_ROW_MAJOR && p->precision != RLU_PREC_F64) {
-    // reduced-precision contraction with one refinement step; writes Bt
-    if ((rs = run_precision_contraction(cx, fp, A, p, ws, st)) != RLU_OK) return rs;
+  if (A->layout == RLU_DENSE_ROW_MAJOR && p->precision == RLU_PREC_BF16_REFINED) {
+    // one refinement step of the BF16 contraction; writes Bt
+    e = precision_refine(fp.pp, A, l, Wt, at<double>(ws, fp.Ginv), at<double>(ws, fp.Bt), at<void>(ws, fp.prec), st);
+    if (e != hipSuccess) return hip_fail(e, "refinement");
   } else {  // B^T = W^T G^{-1}
     GemmArgs g{};
     g.M = n; g.N = l; g.K = l;

@@ -1,13 +1,19 @@
-// FP64 GEMM on CDNA MFMA (v_mfma_f64_16x16x4_f64) for the dense
-// contractions of the least-squares product (Corollary 3.2's B = L_y^+ P A):
+// GEMM on CDNA MFMA for the dense contractions of the least-squares product
+// (Corollary 3.2's B = L_y^+ P A):
 //   W^T = A^T Lhat  (n x l, the dominant contraction, K = m),
 //   G   = Lhat^T Lhat, and the small l x l / n x l / m x l products.
+// FP64 (v_mfma_f64_16x16x4_f64) throughout, or, for the FP32 form of the
+// contraction, FP32 operands and accumulation (v_mfma_f32_16x16x4_f32).
 //
-// Block tile 64 (M) x 16*TN (N), K staged through LDS 32 at a time with
-// the next tile's global loads in flight (in registers) during the MFMAs of
-// the current one; the four waves of a block each own 16 rows of the tile
-// and TN 16x16 accumulators.  op(A) is A (M x K, row major, optional row gather) or A^T
-// (A stored K x M).  A may be FP32 storage, widened exactly to FP64 on load.
+// Block: four waves in a 2 x 2 grid, each owning FM x FN 16x16 accumulator
+// tiles, so the block tile is (32 FM) x (32 FN).  K advances 16 at a time
+// through a double-buffered LDS tile: the global loads of stage s + 1 are
+// issued before the MFMAs of stage s and written to the other buffer after
+// them, one barrier per stage.  Every global load is issued unconditionally
+// from an in-bounds address (out-of-range elements read the tile's first
+// row / column and are replaced by zero), so a stage's loads are all in
+// flight together.  op(A) is A (M x K, row major, optional row gather) or
+// A^T (A stored K x M); A may be FP32 storage (widened exactly for FP64).
 // Split-K writes per-split partials that a second kernel sums in a fixed
 // order (deterministic).
 #include "rlu_device.h"
@@ -16,13 +22,33 @@
 namespace rlu {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Accumulator and MFMA of one compute type.  Result layouts (lane l, element
+// v): FP64 16x16x4 holds D[l/16 + 4v][l%16], FP32 16x16x4 holds
+// D[4(l/16) + v][l%16]; both take A[l%16][l/16] and B[l/16][l%16].
+template <typename TC> struct Mfma;
+template <> struct Mfma<double> {
+  typedef v4d acc_t;
+  static __device__ inline acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <> struct Mfma<float> {
+  typedef v4f acc_t;
+  static __device__ inline acc_t step(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
 
 struct GemmK {
   int64_t M, N, K;
   const void *A;
   int64_t lda;
   const int32_t *gather;
-  const double *B;
+  const void *B;
   int64_t ldb;
   double *C;
   int64_t ldc;
@@ -32,112 +58,151 @@ struct GemmK {
   int partial;
 };
 
-constexpr int kBM = 64, kBK = 32;
+constexpr int kBK = 16;
 
-// LDS row strides (doubles) congruent to 16 mod 32, i.e. 128 bytes mod 256:
-// the four 16-lane groups of an MFMA operand read (rows k..k+3) then fall on
-// two disjoint halves of the banks, the minimum of two passes per read.
+// LDS row stride congruent to 16 mod 32 elements: the four 16-lane groups of
+// an operand read (rows k .. k+3) then fall on two disjoint halves of the banks.
 constexpr int pad_stride(int w) { return w + ((16 - (w % 32)) + 32) % 32; }
 
-template <typename TAt, bool TRA, bool GATH, int TN>
-__global__ __launch_bounds__(256) void k_gemm_f64(GemmK p) {
-  constexpr int BN = 16 * TN;
-  constexpr int AS = pad_stride(kBM);
-  constexpr int BS = pad_stride(BN);
-  constexpr int AR = (kBK * kBM) / 256;  // A elements per thread per tile
-  constexpr int BR = (kBK * BN) / 256;   // B elements per thread per tile
-  __shared__ double As[kBK * AS];
-  __shared__ double Bs[kBK * BS];
+template <typename TC, typename TAt, bool TRA, bool GATH, int FM, int FN>
+__global__ __launch_bounds__(256) void k_gemm(GemmK p) {
+  typedef Mfma<TC> MF;
+  constexpr int BM = 32 * FM, BN = 32 * FN;
+  constexpr int AS = pad_stride(BM), BS = pad_stride(BN);
+  constexpr int AR = (kBK * BM) / 256;  // A elements per thread per stage
+  constexpr int BR = (kBK * BN) / 256;  // B elements per thread per stage
+  __shared__ TC As[2][kBK * AS];
+  __shared__ TC Bs[2][kBK * BS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t m0 = (int64_t)blockIdx.x * kBM, n0 = (int64_t)blockIdx.y * BN;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
   const int64_t kb = (int64_t)blockIdx.z * p.Kc;
   const int64_t ke = min(p.K, kb + p.Kc);
   const TAt *A = reinterpret_cast<const TAt *>(p.A);
-  v4d acc[TN];
-#pragma unroll
-  for (int t = 0; t < TN; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  const TC *B = reinterpret_cast<const TC *>(p.B);
 
+  typename MF::acc_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = typename MF::acc_t{0, 0, 0, 0};
+
+  // Out-of-range elements are read from the tile's first row / column (in
+  // bounds) and zeroed only when the stage is written to LDS, after the
+  // MFMAs, so no instruction consumes a load before the MFMAs have run.
   TAt ra[AR];
-  double rb[BR];
+  TC rb[BR];
+  auto a_ok = [&](int r, int64_t k0) {
+    const int e = tid + 256 * r;
+    int k, m;
+    if (TRA) { k = e / BM; m = e % BM; } else { m = e / kBK; k = e % kBK; }
+    return k0 + k < ke && m0 + m < p.M;
+  };
+  auto b_ok = [&](int r, int64_t k0) {
+    const int e = tid + 256 * r;
+    return k0 + e / BN < ke && n0 + e % BN < p.N;
+  };
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int r = 0; r < AR; ++r) {
       const int e = tid + 256 * r;
       int k, m;
-      if (TRA) { k = e >> 6; m = e & 63; } else { m = e >> 5; k = e & 31; }
-      const int64_t gk = k0 + k, gm = m0 + m;
-      TAt v = (TAt)0;
-      if (gk < ke && gm < p.M) {
-        if (TRA) v = A[gk * p.lda + gm];
-        else v = A[(GATH ? (int64_t)p.gather[gm] : gm) * p.lda + gk];
-      }
-      ra[r] = v;
+      if (TRA) { k = e / BM; m = e % BM; } else { m = e / kBK; k = e % kBK; }
+      const bool ok = a_ok(r, k0);
+      const int64_t ck = ok ? k0 + k : kb, cm = ok ? m0 + m : m0;
+      if (TRA) ra[r] = A[ck * p.lda + cm];
+      else ra[r] = A[(GATH ? (int64_t)p.gather[cm] : cm) * p.lda + ck];
     }
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
       const int e = tid + 256 * r;
-      const int k = e / BN, n = e - k * BN;
-      const int64_t gk = k0 + k, gn = n0 + n;
-      rb[r] = (gk < ke && gn < p.N) ? p.B[gk * p.ldb + gn] : 0.0;
+      const bool ok = b_ok(r, k0);
+      rb[r] = B[(ok ? k0 + e / BN : kb) * p.ldb + (ok ? n0 + e % BN : n0)];
     }
   };
-  auto store = [&]() {
+  auto store = [&](int buf, int64_t k0) {
 #pragma unroll
     for (int r = 0; r < AR; ++r) {
       const int e = tid + 256 * r;
       int k, m;
-      if (TRA) { k = e >> 6; m = e & 63; } else { m = e >> 5; k = e & 31; }
-      As[k * AS + m] = (double)ra[r];
+      if (TRA) { k = e / BM; m = e % BM; } else { m = e / kBK; k = e % kBK; }
+      As[buf][k * AS + m] = a_ok(r, k0) ? (TC)ra[r] : (TC)0;
     }
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
       const int e = tid + 256 * r;
-      const int k = e / BN, n = e - k * BN;
-      Bs[k * BS + n] = rb[r];
+      Bs[buf][(e / BN) * BS + e % BN] = b_ok(r, k0) ? rb[r] : (TC)0;
     }
   };
 
+  int buf = 0;
   if (kb < ke) {
     load(kb);
-    store();
+    store(0, kb);
     __syncthreads();
   }
   for (int64_t k0 = kb; k0 < ke; k0 += kBK) {
     const bool more = k0 + kBK < ke;
     if (more) load(k0 + kBK);  // in flight during the MFMAs below
+    const TC *as = As[buf] + wm * 16 * FM + (lane & 15);
+    const TC *bs = Bs[buf] + wn * 16 * FN + (lane & 15);
 #pragma unroll
     for (int kk = 0; kk < kBK / 4; ++kk) {
-      const double a = As[(kk * 4 + (lane >> 4)) * AS + wave * 16 + (lane & 15)];
+      const int kr = kk * 4 + (lane >> 4);
+      TC a[FM], b[FN];
 #pragma unroll
-      for (int t = 0; t < TN; ++t) {
-        const double b = Bs[(kk * 4 + (lane >> 4)) * BS + t * 16 + (lane & 15)];
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
-      }
+      for (int i = 0; i < FM; ++i) a[i] = as[kr * AS + i * 16];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) b[j] = bs[kr * BS + j * 16];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = MF::step(a[i], b[j], acc[i][j]);
     }
-    __syncthreads();
     if (more) {
-      store();
+      store(buf ^ 1, k0 + kBK);
       __syncthreads();
+      buf ^= 1;
     }
   }
 
+  // beta != 0: the old C values are loaded first (clamped, unconditional)
+  double cold[FM][FN][4];
+  const bool use_old = !p.partial && p.beta != 0.0;
 #pragma unroll
-  for (int t = 0; t < TN; ++t) {
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t m = m0 + wave * 16 + (lane >> 4) + 4 * v;  // D row = lane/16 + 4 v
-      const int64_t n = n0 + t * 16 + (lane & 15);
-      if (m < p.M && n < p.N) {
-        if (p.partial) {
-          p.C[(int64_t)blockIdx.z * p.cstride + m * p.ldc + n] = acc[t][v];
-        } else {
-          double r = p.alpha * acc[t][v];
-          if (p.beta != 0.0) r += p.beta * p.C[m * p.ldc + n];
-          p.C[m * p.ldc + n] = r;
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        cold[i][j][v] = 0.0;
+        if (use_old) {
+          const int64_t m = m0 + wm * 16 * FM + i * 16 + MF::row(lane, v);
+          const int64_t n = n0 + wn * 16 * FN + j * 16 + (lane & 15);
+          const bool ok = m < p.M && n < p.N;
+          const double c = p.C[(ok ? m : m0) * p.ldc + (ok ? n : n0)];
+          cold[i][j][v] = ok ? c : 0.0;
         }
       }
-    }
-  }
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t m = m0 + wm * 16 * FM + i * 16 + MF::row(lane, v);
+        const int64_t n = n0 + wn * 16 * FN + j * 16 + (lane & 15);
+        if (m < p.M && n < p.N) {
+          const double x = (double)acc[i][j][v];
+          if (p.partial) {
+            p.C[(int64_t)blockIdx.z * p.cstride + m * p.ldc + n] = x;
+          } else {
+            double r = p.alpha * x;
+            if (use_old) r += p.beta * cold[i][j][v];
+            p.C[m * p.ldc + n] = r;
+          }
+        }
+      }
 }
 
 __global__ void k_splitk_reduce(int64_t M, int64_t N, int splits, const double *__restrict__ parts,
@@ -154,25 +219,33 @@ __global__ void k_splitk_reduce(int64_t M, int64_t N, int splits, const double *
   }
 }
 
-static int pick_tn(int64_t N) {
-  const int64_t t = ceil_div(N, 16);
-  if (t <= 1) return 1;
-  if (t <= 2) return 2;
-  if (t <= 4) return 4;
-  if (t <= 7) return 7;
-  if (t <= 8) return 8;
-  if (t <= 14) return 14;
-  return 16;
+// Tile shape for an M x N output: FM = 2, and FN (N tile = 32 FN) from
+// 7, 6, 4, 2, 1 minimising padded width x (1 + 1/FN).  The second factor
+// charges narrow tiles for their extra operand reads per MFMA (LDS) and
+// extra passes over op(A) (one per N tile).
+struct Shape {
+  int fm, fn;
+};
+static Shape pick_shape(int64_t M, int64_t N) {
+  (void)M;
+  static const int fns[] = {7, 6, 4, 2, 1};
+  int best = 1;
+  double best_cost = 1e300;
+  for (int fn : fns) {
+    const double cost = (double)(ceil_div(N, 32 * fn) * 32 * fn) * (1.0 + 1.0 / fn);
+    if (cost < best_cost) { best_cost = cost; best = fn; }
+  }
+  return Shape{2, best};
 }
 
-template <typename TAt, bool TRA, bool GATH>
-static hipError_t dispatch_tn(int tn, dim3 grid, GemmK k, hipStream_t st) {
-  switch (tn) {
-#define RLU_TN(T)                                                                            \
-  case T:                                                                                    \
-    hipLaunchKernelGGL((k_gemm_f64<TAt, TRA, GATH, T>), grid, dim3(256), 0, st, k); break;
-    RLU_TN(1) RLU_TN(2) RLU_TN(4) RLU_TN(7) RLU_TN(8) RLU_TN(14) RLU_TN(16)
-#undef RLU_TN
+template <typename TC, typename TAt, bool TRA, bool GATH>
+static hipError_t dispatch_shape(Shape sh, dim3 grid, GemmK k, hipStream_t st) {
+  switch (sh.fn) {
+#define RLU_FN(F)                                                                            \
+  case F:                                                                                    \
+    hipLaunchKernelGGL((k_gemm<TC, TAt, TRA, GATH, 2, F>), grid, dim3(256), 0, st, k); break;
+    RLU_FN(1) RLU_FN(2) RLU_FN(4) RLU_FN(6) RLU_FN(7)
+#undef RLU_FN
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -180,7 +253,7 @@ static hipError_t dispatch_tn(int tn, dim3 grid, GemmK k, hipStream_t st) {
 
 static hipError_t launch(const GemmArgs &g, int splits, int64_t Kc, double *parts, hipStream_t st) {
   if (g.trans_b) return hipErrorInvalidValue;
-  const int tn = pick_tn(g.N);
+  const Shape sh = pick_shape(g.M, g.N);
   GemmK k;
   k.M = g.M; k.N = g.N; k.K = g.K;
   k.A = g.A; k.lda = g.lda; k.gather = g.gather;
@@ -192,15 +265,21 @@ static hipError_t launch(const GemmArgs &g, int splits, int64_t Kc, double *part
   } else {
     k.C = g.C; k.ldc = g.ldc; k.cstride = 0; k.partial = 0;
   }
-  const dim3 grid((unsigned)ceil_div(g.M, kBM), (unsigned)ceil_div(g.N, 16 * tn), (unsigned)splits);
+  const dim3 grid((unsigned)ceil_div(g.M, 32 * sh.fm), (unsigned)ceil_div(g.N, 32 * sh.fn), (unsigned)splits);
+  if (g.compute == RLU_F32) {
+    if (!g.trans_a || g.gather) return hipErrorInvalidValue;
+    if (g.a_dtype == RLU_F32) return dispatch_shape<float, float, true, false>(sh, grid, k, st);
+    return dispatch_shape<float, double, true, false>(sh, grid, k, st);
+  }
+  if (g.compute != RLU_F64) return hipErrorInvalidValue;
   if (g.trans_a) {
     if (g.gather) return hipErrorInvalidValue;
-    if (g.a_dtype == RLU_F32) return dispatch_tn<float, true, false>(tn, grid, k, st);
-    return dispatch_tn<double, true, false>(tn, grid, k, st);
+    if (g.a_dtype == RLU_F32) return dispatch_shape<double, float, true, false>(sh, grid, k, st);
+    return dispatch_shape<double, double, true, false>(sh, grid, k, st);
   }
   if (g.a_dtype != RLU_F64) return hipErrorInvalidValue;
-  if (g.gather) return dispatch_tn<double, false, true>(tn, grid, k, st);
-  return dispatch_tn<double, false, false>(tn, grid, k, st);
+  if (g.gather) return dispatch_shape<double, double, false, true>(sh, grid, k, st);
+  return dispatch_shape<double, double, false, false>(sh, grid, k, st);
 }
 
 hipError_t gemm_f64(const GemmArgs &g, hipStream_t st) {
@@ -209,9 +288,9 @@ hipError_t gemm_f64(const GemmArgs &g, hipStream_t st) {
 }
 
 int choose_splits(int64_t M, int64_t N, int64_t K, int num_cu) {
-  const int tn = pick_tn(N);
-  const int64_t tiles = ceil_div(M, kBM) * ceil_div(N, 16 * tn);
-  int64_t s = ceil_div((int64_t)num_cu, tiles);  // one block per CU (register bound)
+  const Shape sh = pick_shape(M, N);
+  const int64_t tiles = ceil_div(M, 32 * sh.fm) * ceil_div(N, 32 * sh.fn);
+  int64_t s = ceil_div((int64_t)num_cu, tiles);  // about one block per CU (register bound)
   s = std::min<int64_t>(s, std::max<int64_t>(1, K / 256));
   s = std::min<int64_t>(s, 64);
   return (int)std::max<int64_t>(1, s);

@@ -4,12 +4,6 @@
 
 namespace rlu {
 
-struct FactorPlan;
-size_t precision_scratch_bytes(int64_t, int64_t, int, int, int) { return 0; }
-rlu_status run_precision_contraction(const rlu_ctx_impl &, const FactorPlan &, const rlu_matrix *,
-                                     const rlu_params *, void *, hipStream_t) {
-  return fail(RLU_ERR_INVALID_ARG, "reduced-precision contraction is not available in this build");
-}
 void serve_shutdown(rlu_ctx_impl &) {}
 
 }  // namespace rlu

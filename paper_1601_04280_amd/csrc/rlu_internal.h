@@ -73,14 +73,17 @@ hipError_t launch_gepp(int64_t rows, int cols, const double *X, int64_t ldx, dou
                        int32_t *perm, int32_t *ipiv, void *ws, int32_t *abort_flag, rlu_info *info,
                        int which, const GeppPlan &plan, hipStream_t st);
 
-// ---- FP64 GEMM on MFMA ------------------------------------------------------------
-// C (M x N, ldc) = alpha * op(A) * op(B) + beta * C, or split-K partials.
+// ---- GEMM on MFMA ----------------------------------------------------------------
+// C (M x N, ldc, FP64) = alpha * op(A) * op(B) + beta * C, or split-K partials.
+// compute = RLU_F64: FP64 operands and MFMA.  compute = RLU_F32: B is FP32,
+// op(A) (transposed only) is rounded to FP32, FP32 MFMA and accumulation.
 struct GemmArgs {
   int64_t M, N, K;
   const void *A; int64_t lda; int a_dtype; bool trans_a; const int32_t *gather;
-  const double *B; int64_t ldb; bool trans_b;
+  const void *B; int64_t ldb; bool trans_b;
   double *C; int64_t ldc;
   double alpha, beta;
+  int compute;
 };
 // Plain (no split): writes C directly.
 hipError_t gemm_f64(const GemmArgs &g, hipStream_t st);
@@ -90,6 +93,28 @@ hipError_t gemm_f64(const GemmArgs &g, hipStream_t st);
 size_t gemm_f64_splitk_scratch(int64_t M, int64_t N, int splits);
 hipError_t gemm_f64_splitk(const GemmArgs &g, int splits, double *parts, hipStream_t st);
 int choose_splits(int64_t M, int64_t N, int64_t K, int num_cu);
+
+// ---- reduced-precision contraction ------------------------------------------------
+// Scratch offsets (bytes, relative to the form's scratch base) and shapes.
+struct PrecPlan {
+  int precision;
+  int lp;              // l rounded up to 32: row stride of the BF16 operands
+  int64_t mp;          // m rounded up to 64: row stride of Lhat^T and R^T
+  int64_t np_rows;     // rows of Lhat^T (l rounded up to 128)
+  int wm, wn;          // BF16 GEMM tile (32 wm x 32 wn)
+  int splits;          // K splits of that GEMM
+  int64_t Kc;          // K extent of one split
+  size_t lhi, llo, lht, xhi, xlo, r, parts, lf;
+  size_t total;
+};
+bool plan_precision(int64_t m, int64_t n, int l, int precision, int num_cu, PrecPlan *pp);
+// W^T (n x l) = A^T Lhat in the plan's precision (BF16: the first pass W0^T).
+// FP32 uses `parts64` (splits_w partials of n x l doubles) when splits_w > 1.
+hipError_t precision_contract(const PrecPlan &pp, const rlu_matrix *A, const double *Lhat, int l, double *Wt,
+                              double *parts64, int splits_w, void *scratch, hipStream_t st);
+// BF16 only: B^T = X0^T + dW^T G^{-1} from W0^T (overwritten) and G^{-1}.
+hipError_t precision_refine(const PrecPlan &pp, const rlu_matrix *A, int l, double *Wt, const double *Ginv,
+                            double *Bt, void *scratch, hipStream_t st);
 
 // ---- small dense FP64 pieces ---------------------------------------------------------
 // In place: G (l x l, ld l, SPD) -> Linv = inverse of the Cholesky factor
