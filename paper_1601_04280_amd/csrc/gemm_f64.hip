@@ -5,8 +5,10 @@
 // FP64 (v_mfma_f64_16x16x4_f64) throughout, or, for the FP32 form of the
 // contraction, FP32 operands and accumulation (v_mfma_f32_16x16x4_f32).
 //
-// Block: four waves in a 2 x 2 grid, each owning FM x FN 16x16 accumulator
-// tiles, so the block tile is (32 FM) x (32 FN).  K advances 16 at a time
+// Block: WGM x 2 waves (WGM = 4 for large outputs: two waves per SIMD, so one
+// wave's LDS waits and barrier are covered by the other's MFMAs; 2 for small
+// ones), each owning FM x FN 16x16 accumulator tiles, so the block tile is
+// (16 FM WGM) x (32 FN).  K advances 16 at a time
 // through a double-buffered LDS tile: the global loads of stage s + 1 are
 // issued before the MFMAs of stage s and written to the other buffer after
 // them, one barrier per stage.  Every global load is issued unconditionally
@@ -64,17 +66,19 @@ constexpr int kBK = 16;
 // an operand read (rows k .. k+3) then fall on two disjoint halves of the banks.
 constexpr int pad_stride(int w) { return w + ((16 - (w % 32)) + 32) % 32; }
 
-template <typename TC, typename TAt, bool TRA, bool GATH, int FM, int FN>
-__global__ __launch_bounds__(256) void k_gemm(GemmK p) {
+template <typename TC, typename TAt, bool TRA, bool GATH, int WGM, int FM, int FN>
+__global__ __launch_bounds__(128 * WGM, 1) void k_gemm(GemmK p) {
   typedef Mfma<TC> MF;
-  constexpr int BM = 32 * FM, BN = 32 * FN;
+  constexpr int NT = 128 * WGM;  // threads: WGM x 2 waves
+  constexpr int BM = 16 * FM * WGM, BN = 32 * FN;
   constexpr int AS = pad_stride(BM), BS = pad_stride(BN);
-  constexpr int AR = (kBK * BM) / 256;  // A elements per thread per stage
-  constexpr int BR = (kBK * BN) / 256;  // B elements per thread per stage
+  constexpr int AR = (kBK * BM) / NT;  // A elements per thread per stage
+  constexpr int BR = (kBK * BN) / NT;  // B elements per thread per stage
+  static_assert((kBK * BM) % NT == 0 && (kBK * BN) % NT == 0, "stage not divisible among threads");
   __shared__ TC As[2][kBK * AS];
   __shared__ TC Bs[2][kBK * BS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave % WGM, wn = wave / WGM;
   const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
   const int64_t kb = (int64_t)blockIdx.z * p.Kc;
   const int64_t ke = min(p.K, kb + p.Kc);
@@ -93,19 +97,19 @@ __global__ __launch_bounds__(256) void k_gemm(GemmK p) {
   TAt ra[AR];
   TC rb[BR];
   auto a_ok = [&](int r, int64_t k0) {
-    const int e = tid + 256 * r;
+    const int e = tid + NT * r;
     int k, m;
     if (TRA) { k = e / BM; m = e % BM; } else { m = e / kBK; k = e % kBK; }
     return k0 + k < ke && m0 + m < p.M;
   };
   auto b_ok = [&](int r, int64_t k0) {
-    const int e = tid + 256 * r;
+    const int e = tid + NT * r;
     return k0 + e / BN < ke && n0 + e % BN < p.N;
   };
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int r = 0; r < AR; ++r) {
-      const int e = tid + 256 * r;
+      const int e = tid + NT * r;
       int k, m;
       if (TRA) { k = e / BM; m = e % BM; } else { m = e / kBK; k = e % kBK; }
       const bool ok = a_ok(r, k0);
@@ -115,7 +119,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmK p) {
     }
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
-      const int e = tid + 256 * r;
+      const int e = tid + NT * r;
       const bool ok = b_ok(r, k0);
       rb[r] = B[(ok ? k0 + e / BN : kb) * p.ldb + (ok ? n0 + e % BN : n0)];
     }
@@ -123,14 +127,14 @@ __global__ __launch_bounds__(256) void k_gemm(GemmK p) {
   auto store = [&](int buf, int64_t k0) {
 #pragma unroll
     for (int r = 0; r < AR; ++r) {
-      const int e = tid + 256 * r;
+      const int e = tid + NT * r;
       int k, m;
       if (TRA) { k = e / BM; m = e % BM; } else { m = e / kBK; k = e % kBK; }
       As[buf][k * AS + m] = a_ok(r, k0) ? (TC)ra[r] : (TC)0;
     }
 #pragma unroll
     for (int r = 0; r < BR; ++r) {
-      const int e = tid + 256 * r;
+      const int e = tid + NT * r;
       Bs[buf][(e / BN) * BS + e % BN] = b_ok(r, k0) ? rb[r] : (TC)0;
     }
   };
@@ -219,15 +223,16 @@ __global__ void k_splitk_reduce(int64_t M, int64_t N, int splits, const double *
   }
 }
 
-// Tile shape for an M x N output: FM = 2, and FN (N tile = 32 FN) from
-// 7, 6, 4, 2, 1 minimising padded width x (1 + 1/FN).  The second factor
-// charges narrow tiles for their extra operand reads per MFMA (LDS) and
-// extra passes over op(A) (one per N tile).
+// Tile shape for an M x N output.  FN (N tile = 32 FN) from 7, 6, 4, 2, 1
+// minimises padded width x (1 + 1/FN): the second factor charges narrow
+// tiles for their extra operand reads per MFMA and extra passes over op(A)
+// (one per N tile).  FM = 2; the 8-wave block (M tile 128) when M is large.
 struct Shape {
-  int fm, fn;
+  int wgm, fm, fn;
+  int bm() const { return 16 * fm * wgm; }
+  int bn() const { return 32 * fn; }
 };
 static Shape pick_shape(int64_t M, int64_t N) {
-  (void)M;
   static const int fns[] = {7, 6, 4, 2, 1};
   int best = 1;
   double best_cost = 1e300;
@@ -235,20 +240,29 @@ static Shape pick_shape(int64_t M, int64_t N) {
     const double cost = (double)(ceil_div(N, 32 * fn) * 32 * fn) * (1.0 + 1.0 / fn);
     if (cost < best_cost) { best_cost = cost; best = fn; }
   }
-  return Shape{2, best};
+  return Shape{M >= 1024 ? 4 : 2, 2, best};
 }
 
-template <typename TC, typename TAt, bool TRA, bool GATH>
-static hipError_t dispatch_shape(Shape sh, dim3 grid, GemmK k, hipStream_t st) {
+template <typename TC, typename TAt, bool TRA, bool GATH, int WGM>
+static hipError_t dispatch_fn(const Shape &sh, dim3 grid, GemmK k, hipStream_t st) {
   switch (sh.fn) {
-#define RLU_FN(F)                                                                            \
-  case F:                                                                                    \
-    hipLaunchKernelGGL((k_gemm<TC, TAt, TRA, GATH, 2, F>), grid, dim3(256), 0, st, k); break;
+#define RLU_FN(F)                                                                                \
+  case F:                                                                                        \
+    hipLaunchKernelGGL((k_gemm<TC, TAt, TRA, GATH, WGM, 2, F>), grid, dim3(128 * WGM), 0, st, k); \
+    break;
     RLU_FN(1) RLU_FN(2) RLU_FN(4) RLU_FN(6) RLU_FN(7)
 #undef RLU_FN
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename TC, typename TAt, bool TRA, bool GATH>
+static hipError_t dispatch_shape(const Shape &sh, dim3 grid, GemmK k, hipStream_t st) {
+  if (sh.fm != 2) return hipErrorInvalidValue;
+  if (sh.wgm == 4) return dispatch_fn<TC, TAt, TRA, GATH, 4>(sh, grid, k, st);
+  if (sh.wgm == 2) return dispatch_fn<TC, TAt, TRA, GATH, 2>(sh, grid, k, st);
+  return hipErrorInvalidValue;
 }
 
 static hipError_t launch(const GemmArgs &g, int splits, int64_t Kc, double *parts, hipStream_t st) {
@@ -265,7 +279,7 @@ static hipError_t launch(const GemmArgs &g, int splits, int64_t Kc, double *part
   } else {
     k.C = g.C; k.ldc = g.ldc; k.cstride = 0; k.partial = 0;
   }
-  const dim3 grid((unsigned)ceil_div(g.M, 32 * sh.fm), (unsigned)ceil_div(g.N, 32 * sh.fn), (unsigned)splits);
+  const dim3 grid((unsigned)ceil_div(g.M, sh.bm()), (unsigned)ceil_div(g.N, sh.bn()), (unsigned)splits);
   if (g.compute == RLU_F32) {
     if (!g.trans_a || g.gather) return hipErrorInvalidValue;
     if (g.a_dtype == RLU_F32) return dispatch_shape<float, float, true, false>(sh, grid, k, st);
@@ -287,13 +301,20 @@ hipError_t gemm_f64(const GemmArgs &g, hipStream_t st) {
   return launch(g, 1, std::max<int64_t>(g.K, 1), nullptr, st);
 }
 
+// K splits: the count (1 .. 64, each split at least 256 deep) that minimises
+// rounds of co-resident blocks (one per CU) per unit of work; ties go to
+// fewer splits.
 int choose_splits(int64_t M, int64_t N, int64_t K, int num_cu) {
   const Shape sh = pick_shape(M, N);
-  const int64_t tiles = ceil_div(M, 32 * sh.fm) * ceil_div(N, 32 * sh.fn);
-  int64_t s = ceil_div((int64_t)num_cu, tiles);  // about one block per CU (register bound)
-  s = std::min<int64_t>(s, std::max<int64_t>(1, K / 256));
-  s = std::min<int64_t>(s, 64);
-  return (int)std::max<int64_t>(1, s);
+  const int64_t tiles = ceil_div(M, sh.bm()) * ceil_div(N, sh.bn());
+  const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(64, K / 256));
+  int64_t best = 1;
+  double best_cost = 1e300;
+  for (int64_t s = 1; s <= smax; ++s) {
+    const double cost = (double)ceil_div(tiles * s, (int64_t)num_cu) / (double)s;
+    if (cost < best_cost - 1e-12) { best_cost = cost; best = s; }
+  }
+  return (int)best;
 }
 
 size_t gemm_f64_splitk_scratch(int64_t M, int64_t N, int splits) {
