@@ -21,7 +21,8 @@
 //      always x[0]), so a step is a straight-line x[k] = x[k+1] - m * p[k+1]
 //      with static register indices, and the multiplier goes straight to L.
 //   2. k_u12: U12 = L11^{-1} X[pivot rows, panel end:], a small triangular
-//      solve (also the U output rows of the panel).
+//      solve, four lanes of a wave per column (also the U output rows of the
+//      panel).
 //   3. the trailing update X[:, panel end:] -= L[:, panel] U12 on the FP64
 //      MFMA GEMM.
 #include "rlu_device.h"
@@ -301,39 +302,53 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
   }
 }
 
-// U12 = L11^{-1} X[pivot rows, j1:] for 64 columns per block: L11 and the
-// pivot rows' values are staged in LDS, then the forward substitution runs
-// with four threads per column.  Also the U output rows [j0, j1), columns j1:.
+// U12 = L11^{-1} X[pivot rows, j1:] for 64 columns per block, four lanes of
+// one wave per column: L11 (unit lower, the panel's multipliers on its own
+// pivot rows) sits in LDS; lane `part` holds the column's entries 4q + part
+// in registers.  Row i's correction is summed in four interleaved partial
+// sums, combined with two shuffles, and applied by the lane that owns row i:
+// no block barrier inside the substitution.  Also the U output rows
+// [j0, j1), columns j1:.
+template <int NB>
 __global__ __launch_bounds__(256) void k_u12(int l, int j0, int nbp, const double *__restrict__ Lhat,
                                              const int32_t *__restrict__ rowAt, const double *__restrict__ X,
                                              int64_t ldx, double *__restrict__ U) {
-  constexpr int NBMAX = 64, CW = 64;
-  __shared__ double L11[NBMAX][NBMAX + 1];
-  __shared__ double S[NBMAX][CW + 1];
+  constexpr int Q = NB / 4;
+  __shared__ double L11[NB][NB + 1];
   const int tid = threadIdx.x;
-  const int j1 = j0 + nbp, J2 = l - j1;
-  const int cbase = blockIdx.x * CW;
-  for (int e = tid; e < NBMAX * NBMAX; e += 256) {
-    const int t = e / NBMAX, tp = e - t * NBMAX;
+  const int j1 = j0 + nbp;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int t = e / NB, tp = e - t * NB;
     L11[t][tp] = (t < nbp && tp < t) ? Lhat[(int64_t)rowAt[j0 + t] * l + j0 + tp] : 0.0;
-  }
-  for (int e = tid; e < NBMAX * CW; e += 256) {
-    const int t = e / CW, k = e - t * CW;
-    S[t][k] = (t < nbp && cbase + k < J2) ? X[(int64_t)rowAt[j0 + t] * ldx + j1 + cbase + k] : 0.0;
   }
   __syncthreads();
   const int col = tid >> 2, part = tid & 3;
-  for (int t = 1; t < nbp; ++t) {
+  const int c = j1 + blockIdx.x * 64 + col;
+  const bool active = c < l;
+  double xs[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int i = 4 * q + part;
+    xs[q] = (active && i < nbp) ? X[(int64_t)rowAt[j0 + i] * ldx + c] : 0.0;
+  }
+#pragma unroll
+  for (int i = 1; i < NB; ++i) {
     double acc = 0.0;
-    for (int tp = part; tp < t; tp += 4) acc += L11[t][tp] * S[tp][col];
+#pragma unroll
+    for (int q = 0; q <= (i - 1) / 4; ++q) {
+      const int u = 4 * q + part;
+      if (u < i) acc += L11[i][u] * xs[q];
+    }
     acc += __shfl_xor(acc, 1, 64);
     acc += __shfl_xor(acc, 2, 64);
-    if (part == 0) S[t][col] -= acc;
-    __syncthreads();
+    if (part == (i & 3)) xs[i >> 2] -= acc;
   }
-  for (int e = tid; e < nbp * CW; e += 256) {
-    const int t = e / CW, k = e - t * CW;
-    if (cbase + k < J2) U[(size_t)(j0 + t) * l + j1 + cbase + k] = S[t][k];
+  if (active) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int i = 4 * q + part;
+      if (i < nbp) U[(int64_t)(j0 + i) * l + c] = xs[q];
+    }
   }
 }
 
@@ -429,8 +444,14 @@ hipError_t launch_gepp(int64_t rows, int cols, const double *X, int64_t ldx, dou
     if (e != hipSuccess) return e;
     if (j1 >= cols) break;
     const int J2 = cols - j1;
-    hipLaunchKernelGGL(k_u12, dim3((unsigned)ceil_div(J2, 64)), dim3(256), 0, st, cols, j0, nbp, Lhat, rowAt,
-                       src, ldsrc, U);
+    const dim3 ug((unsigned)ceil_div(J2, 64));
+    switch (plan.nb) {
+      case 64: hipLaunchKernelGGL(k_u12<64>, ug, dim3(256), 0, st, cols, j0, nbp, Lhat, rowAt, src, ldsrc, U); break;
+      case 32: hipLaunchKernelGGL(k_u12<32>, ug, dim3(256), 0, st, cols, j0, nbp, Lhat, rowAt, src, ldsrc, U); break;
+      case 16: hipLaunchKernelGGL(k_u12<16>, ug, dim3(256), 0, st, cols, j0, nbp, Lhat, rowAt, src, ldsrc, U); break;
+      case 8: hipLaunchKernelGGL(k_u12<8>, ug, dim3(256), 0, st, cols, j0, nbp, Lhat, rowAt, src, ldsrc, U); break;
+      default: return hipErrorInvalidValue;
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // trailing update: Wk[:, j1:] -= Lhat[:, j0:j1] U[j0:j1, j1:]
     GemmArgs gm{};
