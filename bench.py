@@ -17,7 +17,13 @@ Unless --no-extras, the line also carries
            FP64, FP32 and BF16 + one refinement step, side by side, each with
            its relative residual ||LU - PAQ||_F / ||A||_F;
   `csr`:   the 200000 x 100000 CSR matrix at 0.1% density with a rank-50
-           plant (k = 100, l = 110, s = 4096).
+           plant (k = 100, l = 110, s = 4096);
+  `serving`: the request mix through the continuous-batching loop: m
+           log-uniform in [512, 8192], n in [256, 4096], k in {16 .. 256},
+           l = k + 10, s = min(n, 8k), 30% BF16-refined, dense
+           low-rank-plus-noise (sigma_i = 2^-(i-1), r = 20, noise 1e-10);
+           Poisson arrivals at 0.5, 0.7 and 0.9 of the measured saturated
+           rate, p50 / p99 latency (completion - arrival) and decomps/s.
 """
 from __future__ import annotations
 
@@ -203,6 +209,73 @@ def csr_block(rlu, ctx, dev):
     return res
 
 
+def serve_block(rlu, dev, counts=(600, 2000, 600), fracs=(0.5, 0.7, 0.9), n_sat=400, max_inflight=8):
+    import numpy as np
+    import torch
+    import synth
+    shapes = synth.serving_shapes(max(counts + (n_sat,)), seed=7)
+    # requests take top-left blocks of four 8192 x 4096 low-rank-plus-noise matrices
+    base = [synth.lowrank_dense_torch(8192, 4096, synth.spectrum_geometric(20), 1000 + i, noise=1e-10, device=dev)
+            for i in range(4)]
+    torch.cuda.synchronize()
+    infos = []
+    srv = rlu.Server(hbm_budget_bytes=16 << 30, max_inflight=max_inflight)
+
+    def submit(i):
+        sh = shapes[i]
+        out = rlu.alloc_factors(sh["m"], sh["n"], sh["l"], 0)
+        infos.append(out.info)
+        return srv.submit(base[i % 4][: sh["m"], : sh["n"]], k=sh["k"], l=sh["l"], s=sh["s"], seed=SEED + i,
+                          precision=sh["precision"], out=out, sync_inputs=False)
+
+    def run(arrivals):
+        count = len(arrivals)
+        outstanding, lat = {}, np.zeros(count)
+        i = done = 0
+        t0 = time.perf_counter()
+        while done < count:
+            now = time.perf_counter() - t0
+            while i < count and arrivals[i] <= now:
+                outstanding[submit(i)] = i
+                i += 1
+            for t in list(outstanding):
+                if srv.poll(t) is not None:
+                    j = outstanding.pop(t)
+                    lat[j] = time.perf_counter() - t0 - arrivals[j]
+                    done += 1
+            if not outstanding and i < count:
+                time.sleep(max(0.0, min(1e-3, arrivals[i] - (time.perf_counter() - t0))))
+        wall = time.perf_counter() - t0
+        return wall, lat
+
+    run(np.zeros(16))                                          # warm-up
+    wall, _ = run(np.zeros(n_sat))                             # saturated: everything queued at t = 0
+    sat = n_sat / wall
+    res = {"workload": "serving_mix", "max_inflight": max_inflight, "pool_bytes": 16 << 30,
+           "saturated_decomps_per_s": round(sat, 2), "bf16_fraction": round(
+               sum(sh["precision"] == "bf16" for sh in shapes[: max(counts)]) / max(counts), 3), "runs": []}
+    rng = np.random.default_rng(SEED + 1)
+    for frac, count in zip(fracs, counts):
+        rate = frac * sat
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, count))
+        wall, lat = run(arrivals)
+        res["runs"].append({"rate_frac": frac, "rate_per_s": round(rate, 2), "requests": count,
+                            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                            "mean_ms": round(float(lat.mean()) * 1e3, 3),
+                            "decomps_per_s": round(count / wall, 2)})
+        print(f"# serving {frac:.1f} x saturated ({rate:.0f}/s): p50 {res['runs'][-1]['p50_ms']} ms, "
+              f"p99 {res['runs'][-1]['p99_ms']} ms", file=sys.stderr, flush=True)
+    srv.stop()
+    bad = int((torch.stack(infos)[:, 0] != 0).sum().item())
+    if bad:
+        raise SystemExit(f"{bad} served requests reported a device-side failure")
+    res["requests_checked"] = len(infos)
+    del base
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -270,6 +343,7 @@ def main():
     if not args.no_extras:
         line["forms"] = forms_block(rlu, ctx, dev)
         line["csr"] = csr_block(rlu, ctx, dev)
+        line["serving"] = serve_block(rlu, dev)
     print(json.dumps(line), flush=True)
 
 

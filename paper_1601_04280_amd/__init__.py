@@ -18,7 +18,8 @@ from dataclasses import dataclass
 from typing import Optional
 
 __all__ = [
-    "RluError", "Context", "Factorization", "sketch_params", "sketch", "factor", "tall_lu",
+    "RluError", "Context", "Factorization", "Server", "alloc_factors", "workspace_size", "sketch_params", "sketch", "factor",
+    "tall_lu",
     "library_path", "load_library", "PRECISIONS",
 ]
 
@@ -259,6 +260,37 @@ class Factorization:
                 "timeouts": v[4], "bad_index": v[5]}
 
 
+def workspace_size(A=None, *, k: int, l: int, s: int, precision: str = "f64", csr=None, ctx: Context = None) -> int:
+    """Bytes of workspace one decomposition of this problem needs."""
+    ctx = ctx or default_context()
+    mat = _dense_matrix(A) if csr is None else _csr_matrix(*csr)
+    p = _params(k, l, s, 0, precision)
+    nbytes = ctypes.c_size_t()
+    _check(load_library().rlu_workspace_size(ctx.handle, ctypes.byref(mat), ctypes.byref(p), ctypes.byref(nbytes)))
+    return nbytes.value
+
+
+def alloc_factors(m: int, n: int, l: int, device: int = 0, keep_intermediates: bool = False) -> Factorization:
+    """Output buffers of one decomposition on the device."""
+    torch = _torch()
+    dev = f"cuda:{device}"
+    f64, i32 = torch.float64, torch.int32
+    return Factorization(
+        L=torch.empty(m, l, dtype=f64, device=dev), U=torch.empty(l, n, dtype=f64, device=dev),
+        perm_r=torch.empty(m, dtype=i32, device=dev), perm_c=torch.empty(n, dtype=i32, device=dev),
+        ipiv_r=torch.empty(l, dtype=i32, device=dev), ipiv_c=torch.empty(l, dtype=i32, device=dev),
+        Y=torch.empty(m, l, dtype=f64, device=dev) if keep_intermediates else None,
+        Uy=torch.empty(l, l, dtype=f64, device=dev) if keep_intermediates else None,
+        B=torch.empty(l, n, dtype=f64, device=dev) if keep_intermediates else None,
+        info=torch.zeros(8, dtype=i32, device=dev))
+
+
+def _factors(out: Factorization) -> Factors:
+    return Factors(out.L.data_ptr(), out.L.stride(0), out.U.data_ptr(), out.U.stride(0), out.perm_r.data_ptr(),
+                   out.perm_c.data_ptr(), _ptr(out.ipiv_r), _ptr(out.ipiv_c), _ptr(out.Y),
+                   out.Y.stride(0) if out.Y is not None else 0, _ptr(out.Uy), _ptr(out.B), out.info.data_ptr())
+
+
 def factor(A=None, *, k: int, l: int, s: int, seed: int, precision: str = "f64", csr=None,
            ctx: Context = None, keep_intermediates: bool = False, check: bool = True, flags: int = 0,
            out: Factorization = None) -> Factorization:
@@ -272,20 +304,9 @@ def factor(A=None, *, k: int, l: int, s: int, seed: int, precision: str = "f64",
     nbytes = ctypes.c_size_t()
     _check(lib.rlu_workspace_size(ctx.handle, ctypes.byref(mat), ctypes.byref(p), ctypes.byref(nbytes)))
     ws, wsb = ctx.workspace(nbytes.value)
-    dev = f"cuda:{ctx.device}"
     if out is None:
-        f64, i32 = torch.float64, torch.int32
-        out = Factorization(
-            L=torch.empty(m, l, dtype=f64, device=dev), U=torch.empty(l, n, dtype=f64, device=dev),
-            perm_r=torch.empty(m, dtype=i32, device=dev), perm_c=torch.empty(n, dtype=i32, device=dev),
-            ipiv_r=torch.empty(l, dtype=i32, device=dev), ipiv_c=torch.empty(l, dtype=i32, device=dev),
-            Y=torch.empty(m, l, dtype=f64, device=dev) if keep_intermediates else None,
-            Uy=torch.empty(l, l, dtype=f64, device=dev) if keep_intermediates else None,
-            B=torch.empty(l, n, dtype=f64, device=dev) if keep_intermediates else None,
-            info=torch.zeros(8, dtype=i32, device=dev))
-    f = Factors(out.L.data_ptr(), out.L.stride(0), out.U.data_ptr(), out.U.stride(0), out.perm_r.data_ptr(),
-                out.perm_c.data_ptr(), _ptr(out.ipiv_r), _ptr(out.ipiv_c), _ptr(out.Y),
-                out.Y.stride(0) if out.Y is not None else 0, _ptr(out.Uy), _ptr(out.B), out.info.data_ptr())
+        out = alloc_factors(m, n, l, ctx.device, keep_intermediates)
+    f = _factors(out)
     _check(lib.rlu_factor(ctx.handle, ctypes.byref(mat), ctypes.byref(p), ctypes.byref(f), ws, wsb,
                           _stream(ctx.device)))
     if check:
@@ -293,6 +314,71 @@ def factor(A=None, *, k: int, l: int, s: int, seed: int, precision: str = "f64",
         if st != RLU_OK:
             raise RluError(st, f"device-side failure, info={out.info_dict()}")
     return out
+
+
+class Server:
+    """Continuous batching of independent decompositions on one device
+    (rlu_serve_start / rlu_submit / rlu_poll / rlu_serve_stop).
+
+    Inputs and outputs stay referenced here until their ticket retires.  The
+    library runs requests on its own streams: inputs written by torch must be
+    complete before submit (``sync_inputs`` synchronises the current stream).
+    """
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 4, device: int = 0):
+        self.ctx = Context(device)
+        self._live = {}
+        _check(load_library().rlu_serve_start(self.ctx.handle, int(hbm_budget_bytes), int(max_inflight)))
+        self._running = True
+
+    def submit(self, A=None, *, k: int, l: int, s: int, seed: int, precision: str = "f64", csr=None,
+               out: Factorization = None, keep_intermediates: bool = False, sync_inputs: bool = True) -> int:
+        torch = _torch()
+        mat = _dense_matrix(A) if csr is None else _csr_matrix(*csr)
+        p = _params(k, l, s, seed, precision)
+        if out is None:
+            out = alloc_factors(mat.m, mat.n, l, self.ctx.device, keep_intermediates)
+        if sync_inputs:
+            torch.cuda.current_stream(self.ctx.device).synchronize()
+        f = _factors(out)
+        ticket = ctypes.c_uint64(0)
+        _check(load_library().rlu_submit(self.ctx.handle, ctypes.byref(mat), ctypes.byref(p), ctypes.byref(f),
+                                         ctypes.byref(ticket)))
+        self._live[ticket.value] = (A, csr, out)
+        return ticket.value
+
+    def poll(self, ticket: int):
+        """The Factorization once the request is complete, else None; raises on failure."""
+        st = load_library().rlu_poll(self.ctx.handle, ctypes.c_uint64(ticket))
+        if st == RLU_ERR_AGAIN:
+            return None
+        entry = self._live.pop(ticket, None)
+        _check(st)
+        return entry[2] if entry else None
+
+    def wait(self, ticket: int, timeout_s: float = 120.0):
+        import time
+        t0 = time.perf_counter()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError(f"ticket {ticket} not complete after {timeout_s} s")
+            time.sleep(20e-6)
+
+    def stop(self):
+        if self._running:
+            _check(load_library().rlu_serve_stop(self.ctx.handle))
+            self._running = False
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()
+        self.ctx.close()
 
 
 def tall_lu(X, ctx: Context = None, check: bool = True):

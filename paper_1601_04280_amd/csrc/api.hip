@@ -96,19 +96,6 @@ struct Carver {
   }
 };
 
-struct FactorPlan {
-  int64_t m, n;
-  int l, s;
-  GeppPlan py, pb;
-  int splits_w, splits_g;
-  PrecPlan pp;
-  // offsets (bytes) into the workspace
-  size_t ctl, code, sel, twf, twp, Y, slots, csc, Lhat, Uy, Wt, parts, Gm, Linv, Dinv, Ginv, Bt, Lph,
-      Up, Lt, prec;
-  size_t total;
-  size_t sketch_total;
-};
-
 // control words: [1] abort flag of the cooperative launches
 constexpr int kCtlWords = 64;
 

@@ -152,4 +152,22 @@ rlu_status validate_params(const rlu_matrix *A, const rlu_params *p);
 rlu_status validate_factors(const rlu_matrix *A, const rlu_params *p, const rlu_factors *out);
 void serve_shutdown(rlu_ctx_impl &cx);
 
+// ---- the decomposition's stage sequence ------------------------------------------
+struct FactorPlan {
+  int64_t m, n;
+  int l, s;
+  GeppPlan py, pb;
+  int splits_w, splits_g;
+  PrecPlan pp;
+  // offsets (bytes) into the workspace
+  size_t ctl, code, sel, twf, twp, Y, slots, csc, Lhat, Uy, Wt, parts, Gm, Linv, Dinv, Ginv, Bt, Lph,
+      Up, Lt, prec;
+  size_t total;
+  size_t sketch_total;
+};
+rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_params *p, FactorPlan *fp);
+// Enqueue every stage of one decomposition on `st` (arguments validated).
+rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_params *p, const rlu_factors *out,
+                          void *ws, const FactorPlan &fp, hipStream_t st);
+
 }  // namespace rlu

@@ -1,0 +1,120 @@
+"""GPU checks of the serving loop (continuous batching through rlu_submit /
+rlu_poll): every request's factors are the same alone (rlu_factor) and inside
+a mix of concurrently running requests of different shapes and precisions,
+also when a tight HBM pool forces requests to queue and younger ones to pass.
+
+Bar: pivot sequences identical, L and U within 1e-10 relative (Frobenius) of
+the request run alone.  The same kernels run on the same inputs either way;
+only the order of floating-point accumulation inside the dense sketch may
+differ between two runs, so inputs keep every pivot well separated
+(sigma_i = 1/i with rank above l)."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1601_04280_amd as rlu
+import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def make_requests(count, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        m = int(round(math.exp(rng.uniform(math.log(300), math.log(3000)))))
+        n = int(round(math.exp(rng.uniform(math.log(200), math.log(2000)))))
+        k = int(rng.choice([8, 16, 32, 64]))
+        s = min(1 << int(math.floor(math.log2(n))), 8 * k)
+        while k + 10 > min(s, n, m):
+            k //= 2
+            s = min(1 << int(math.floor(math.log2(n))), 8 * k)
+        l = k + 10
+        rank = min(m, n, 3 * l)
+        dtype = np.float32 if i % 5 == 4 else np.float64
+        A = synth.lowrank_dense(m, n, 1.0 / np.arange(1, rank + 1), seed * 1000 + i, dtype=dtype)
+        prec = "bf16" if rng.random() < 0.3 else "f64"
+        reqs.append(dict(A=to_dev(A), k=k, l=l, s=s, seed=seed + i, precision=prec))
+    return reqs
+
+
+def rel(a, b):
+    return (torch.linalg.norm(a - b) / max(torch.linalg.norm(b).item(), 1e-300)).item()
+
+
+def same(g, r):
+    assert torch.equal(g.perm_r, r.perm_r) and torch.equal(g.perm_c, r.perm_c)
+    assert rel(g.L, r.L) <= 1e-10 and rel(g.U, r.U) <= 1e-10
+    assert g.info_dict()["status"] == 0
+
+
+def alone(reqs):
+    return [rlu.factor(r["A"], k=r["k"], l=r["l"], s=r["s"], seed=r["seed"], precision=r["precision"])
+            for r in reqs]
+
+
+def test_alone_equals_mix():
+    reqs = make_requests(14, 11)
+    ref = alone(reqs)
+    torch.cuda.synchronize()
+    with rlu.Server(hbm_budget_bytes=4 << 30, max_inflight=6) as srv:
+        tickets = [srv.submit(r["A"], k=r["k"], l=r["l"], s=r["s"], seed=r["seed"], precision=r["precision"])
+                   for r in reqs]
+        outs = [srv.wait(t) for t in tickets]
+    for g, r in zip(outs, ref):
+        same(g, r)
+
+
+def test_tight_pool_queues_and_backfills():
+    reqs = make_requests(10, 23)
+    sizes = [rlu.workspace_size(r["A"], k=r["k"], l=r["l"], s=r["s"], precision=r["precision"]) for r in reqs]
+    budget = int(max(sizes) * 1.3) + 4096
+    ref = alone(reqs)
+    torch.cuda.synchronize()
+    with rlu.Server(hbm_budget_bytes=budget, max_inflight=3) as srv:
+        tickets = [srv.submit(r["A"], k=r["k"], l=r["l"], s=r["s"], seed=r["seed"], precision=r["precision"])
+                   for r in reqs]
+        outs = [srv.wait(t) for t in tickets]
+    for g, r in zip(outs, ref):
+        same(g, r)
+
+
+def test_serving_errors():
+    A = to_dev(np.random.default_rng(0).standard_normal((500, 400)))
+    big = to_dev(np.random.default_rng(1).standard_normal((3000, 2000)))
+    assert rlu.workspace_size(big, k=64, l=74, s=512) > 1 << 20
+    with rlu.Server(hbm_budget_bytes=1 << 20, max_inflight=2) as srv:
+        with pytest.raises(rlu.RluError) as ei:          # workspace above the pool
+            srv.submit(big, k=64, l=74, s=512, seed=1)
+        assert ei.value.status == 2
+        with pytest.raises(rlu.RluError) as ei:          # never issued
+            srv.poll(987654321)
+        assert ei.value.status == 6
+        lib = rlu.load_library()
+        assert lib.rlu_serve_start(srv.ctx.handle, 1 << 20, 2) == 1   # already serving
+    ctx = rlu.Context(0)
+    mat = rlu._dense_matrix(A)
+    p = rlu._params(20, 30, 64, 1)
+    out = rlu.alloc_factors(500, 400, 30)
+    f = rlu._factors(out)
+    t = ctypes.c_uint64(0)
+    assert lib.rlu_submit(ctx.handle, ctypes.byref(mat), ctypes.byref(p), ctypes.byref(f), ctypes.byref(t)) == 1
+    assert lib.rlu_serve_start(ctx.handle, 1 << 30, 0) == 1            # max_inflight out of range
+    assert lib.rlu_serve_start(ctx.handle, 1 << 30, 2) == 0
+    pt = rlu._params(20, 30, 64, 1, flags=rlu.RLU_FLAG_TIMING)
+    assert lib.rlu_submit(ctx.handle, ctypes.byref(mat), ctypes.byref(pt), ctypes.byref(f), ctypes.byref(t)) == 1
+    assert lib.rlu_submit(ctx.handle, ctypes.byref(mat), ctypes.byref(p), ctypes.byref(f), ctypes.byref(t)) == 0
+    assert lib.rlu_serve_stop(ctx.handle) == 0                         # waits for the request
+    assert lib.rlu_poll(ctx.handle, t.value) == 6                      # stopped: tickets gone
+    torch.cuda.synchronize()
+    assert int(out.info[0].item()) == 0
+    ctx.close()
