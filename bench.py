@@ -56,6 +56,13 @@ def parse():
     ap.add_argument("--precision", choices=["f64", "f32", "bf16"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--gaussian-data", action="store_true",
+                    help="N(0,1) entries of the workload's shape instead of its spectrum (for counter runs: "
+                         "the kernels' memory traffic does not depend on the values, and the profiler "
+                         "cannot run the QR that builds the spectrum)")
+    ap.add_argument("--probe-copy", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES between two device buffers three times (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
     return ap.parse_args()
 
 
@@ -283,13 +290,29 @@ def main():
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.probe_copy:
+        n = max(1, args.probe_copy // 8)
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "copy", "launches": 3, "bytes_read_per_launch": n * 8,
+                          "bytes_written_per_launch": n * 8}), flush=True)
+        return
     import paper_1601_04280_amd as rlu
 
     dev = "cuda:0"
     w = WORKLOADS[args.workload]
     precision = args.precision or w["precision"]
     ctx = rlu.Context(0)
-    A = make_input(args.workload, dev)
+    if args.gaussian_data and args.workload.startswith("dense"):
+        g = torch.Generator(device=dev)
+        g.manual_seed(SEED)
+        dt = torch.float32 if "fp32" in args.workload else torch.float64
+        A = torch.randn(w["m"], w["n"], generator=g, device=dev, dtype=torch.float64).to(dt)
+    else:
+        A = make_input(args.workload, dev)
     torch.cuda.synchronize()
     ms_step, per, out = run(rlu, A, w, precision, args.steps, args.warmup, ctx)
     print(f"# {args.workload} {precision}: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
@@ -326,7 +349,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": precision,
-        "data": "synthetic",
+        "data": "synthetic" if not args.gaussian_data else "synthetic-gaussian",
         "config": {"workload": args.workload, "m": w["m"], "n": w["n"], "k": w["k"], "l": w["l"], "s": w["s"],
                    "storage": storage, "precision": precision},
         "roofline": roof,

@@ -111,7 +111,9 @@ typedef struct {
 } rlu_params;
 
 /* flags */
-#define RLU_FLAG_VALIDATE 1u  /* also check CSR column indices on the device (async) */
+#define RLU_FLAG_VALIDATE 1u  /* CSR: also check on the device (async) that row_ptr never
+                                 * decreases; counted in info.bad_index.  Column indices and
+                                 * row_ptr[0] = 0, row_ptr[m] = nnz are always checked. */
 #define RLU_FLAG_TIMING 2u    /* record HIP events around each stage (rlu_stage_times) */
 
 /* Stages reported by rlu_stage_times, in order. */
@@ -135,7 +137,8 @@ typedef struct {
   int32_t zero_pivots_b;    /* zero pivots in the column-pivoted LU of B            */
   int32_t nonfinite;        /* non-finite values seen by a pivot search             */
   int32_t timeouts;         /* device-wide barriers that gave up (then status != 0) */
-  int32_t bad_index;        /* CSR entries with a column index out of range         */
+  int32_t bad_index;        /* CSR: entries with a column index out of range, plus
+                               row_ptr violations (then status = INVALID_ARG)       */
   int32_t reserved[2];
 } rlu_info;
 
