@@ -191,10 +191,15 @@ rlu_status rlu_tall_lu(rlu_ctx *ctx, const double *X, int64_t rows, int64_t cols
                        void *ws, size_t ws_bytes, void *stream);
 rlu_status rlu_tall_lu_workspace_size(rlu_ctx *ctx, int64_t rows, int64_t cols, size_t *bytes);
 
-/* Per-stage device milliseconds summed over every rlu_factor call made with
- * RLU_FLAG_TIMING on this context since the previous rlu_stage_times call
- * (which waits for those events and then clears them).  ms: host array of
- * RLU_NUM_STAGES floats; calls: host out-param, number of timed calls. */
+/* Per-stage device milliseconds (HIP events at each stage's start and end)
+ * summed over every rlu_factor call made with RLU_FLAG_TIMING on this context
+ * since the previous rlu_stage_times call (which waits for those events and
+ * then clears them).  For a sparse A, or a contraction of at least 1e11
+ * multiply-adds (m n l), the Gram and Cholesky stages run on a second stream
+ * beside the contraction: their intervals then overlap it, and the stage
+ * times add up to more than the call.
+ * ms: host array of RLU_NUM_STAGES floats; calls: host out-param, number of
+ * timed calls. */
 rlu_status rlu_stage_times(rlu_ctx *ctx, float *ms, int *calls);
 
 /* ---- serving: continuous batching of independent decompositions -------- */

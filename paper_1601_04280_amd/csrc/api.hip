@@ -127,8 +127,8 @@ rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_pa
   fp->Lhat = cv.take((size_t)m * l * 8);
   fp->Uy = cv.take((size_t)l * l * 8);
   fp->Wt = cv.take((size_t)n * l * 8);
-  fp->parts = cv.take(std::max(gemm_f64_splitk_scratch(n, l, fp->splits_w),
-                               gemm_f64_splitk_scratch(l, l, fp->splits_g)));
+  fp->parts = cv.take(gemm_f64_splitk_scratch(n, l, fp->splits_w));
+  fp->parts_g = cv.take(gemm_f64_splitk_scratch(l, l, fp->splits_g));  // Gram runs beside the contraction
   fp->Gm = cv.take((size_t)l * l * 8);
   fp->Linv = cv.take((size_t)l * l * 8);
   fp->Dinv = cv.take(chol_scratch_bytes(l));
@@ -183,30 +183,65 @@ static rlu_status run_sketch(const rlu_ctx_impl &cx, const FactorPlan &fp, const
   return e == hipSuccess ? RLU_OK : hip_fail(e, "sketch kernel");
 }
 
-// Stage-boundary events of one timed call (no-ops when timing is off).
+// Start / end events of every stage of one timed call (no-ops when timing is off).
 struct StageMarks {
-  std::array<hipEvent_t, RLU_NUM_STAGES + 1> ev{};
+  std::array<hipEvent_t, 2 * RLU_NUM_STAGES> ev{};
   bool on = false;
-  hipStream_t st = nullptr;
-  void mark(int i) {
-    if (on) hipEventRecord(ev[i], st);
+  void begin(int i, hipStream_t s) {
+    if (on) hipEventRecord(ev[2 * i], s);
+  }
+  void end(int i, hipStream_t s) {
+    if (on) hipEventRecord(ev[2 * i + 1], s);
   }
 };
 
-static rlu_status begin_timing(rlu_ctx_impl &cx, StageMarks &sm, hipStream_t st) {
+static rlu_status begin_timing(rlu_ctx_impl &cx, StageMarks &sm) {
   StageTimer &t = cx.timer;
-  while (t.pool.size() < t.used + RLU_NUM_STAGES + 1) {
+  while (t.pool.size() < t.used + 2 * RLU_NUM_STAGES) {
     hipEvent_t e;
     hipError_t err = hipEventCreate(&e);
     if (err != hipSuccess) return hip_fail(err, "hipEventCreate");
     t.pool.push_back(e);
   }
-  for (int i = 0; i <= RLU_NUM_STAGES; ++i) sm.ev[i] = t.pool[t.used + i];
-  t.used += RLU_NUM_STAGES + 1;
+  for (int i = 0; i < 2 * RLU_NUM_STAGES; ++i) sm.ev[i] = t.pool[t.used + i];
+  t.used += 2 * RLU_NUM_STAGES;
   t.calls.push_back(sm.ev);
   sm.on = true;
-  sm.st = st;
   return RLU_OK;
+}
+
+// The auxiliary stream paired with `st` (created on first use).
+static rlu_status aux_for(rlu_ctx_impl &cx, hipStream_t st, AuxStream *out) {
+  std::lock_guard<std::mutex> g(cx.aux_mu);
+  for (const AuxStream &a : cx.aux)
+    if (a.main == st) {
+      *out = a;
+      return RLU_OK;
+    }
+  AuxStream a;
+  a.main = st;
+  hipError_t e;
+  if ((e = hipStreamCreateWithFlags(&a.aux, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "auxiliary stream");
+  if ((e = hipEventCreateWithFlags(&a.fork, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&a.join, hipEventDisableTiming)) != hipSuccess) {
+    if (a.fork) hipEventDestroy(a.fork);
+    hipStreamDestroy(a.aux);
+    return hip_fail(e, "auxiliary events");
+  }
+  cx.aux.push_back(a);
+  *out = a;
+  return RLU_OK;
+}
+
+void destroy_aux_streams(rlu_ctx_impl &cx) {
+  std::lock_guard<std::mutex> g(cx.aux_mu);
+  for (AuxStream &a : cx.aux) {
+    hipStreamSynchronize(a.aux);
+    hipEventDestroy(a.fork);
+    hipEventDestroy(a.join);
+    hipStreamDestroy(a.aux);
+  }
+  cx.aux.clear();
 }
 
 rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_params *p,
@@ -216,10 +251,13 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   hipError_t e;
   StageMarks sm;
   if (p->flags & RLU_FLAG_TIMING) {
-    rlu_status ts = begin_timing(cx, sm, st);
+    rlu_status ts = begin_timing(cx, sm);
     if (ts != RLU_OK) return ts;
   }
-  sm.mark(RLU_STAGE_PARAMS);
+  AuxStream ax;
+  rlu_status rs = aux_for(cx, st, &ax);
+  if (rs != RLU_OK) return rs;
+  sm.begin(RLU_STAGE_PARAMS, st);
   rlu_info *info = out->info;
   uint32_t *ctl = at<uint32_t>(ws, fp.ctl);
   int32_t *abort_flag = reinterpret_cast<int32_t *>(ctl + 1);
@@ -227,25 +265,62 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   if ((e = launch_fill_u32(ctl, 0u, kCtlWords, st)) != hipSuccess) return hip_fail(e, "fill");
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(info), 0u, sizeof(rlu_info) / 4, st)) != hipSuccess)
     return hip_fail(e, "fill");
-  rlu_status rs = run_params(fp, p, ws, st);
-  if (rs != RLU_OK) return rs;
+  if ((rs = run_params(fp, p, ws, st)) != RLU_OK) return rs;
+  sm.end(RLU_STAGE_PARAMS, st);
 
   double *Y = out->Y ? out->Y : at<double>(ws, fp.Y);
   const int64_t ldy = out->Y ? out->ldy : l;
-  sm.mark(RLU_STAGE_SKETCH);
+  sm.begin(RLU_STAGE_SKETCH, st);
   if ((rs = run_sketch(cx, fp, A, p, Y, ldy, ws, info, st)) != RLU_OK) return rs;
+  sm.end(RLU_STAGE_SKETCH, st);
 
   // Step 3: P Y = L_y U_y (rows of L_y kept in A's order: Lhat = P^T L_y)
   double *Lhat = at<double>(ws, fp.Lhat);
   double *Uy = out->Uy ? out->Uy : at<double>(ws, fp.Uy);
-  sm.mark(RLU_STAGE_LU_Y);
+  sm.begin(RLU_STAGE_LU_Y, st);
   e = launch_gepp(m, l, Y, ldy, Lhat, Uy, out->perm_r, out->ipiv_r, at<void>(ws, fp.slots), abort_flag, info,
                   0, fp.py, st);
   if (e != hipSuccess) return hip_fail(e, "row-pivoted LU launch");
+  sm.end(RLU_STAGE_LU_Y, st);
 
-  // Step 4: W^T = A^T Lhat (n x l) and G = Lhat^T Lhat
+  // Step 4: G = Lhat^T Lhat, its inverse Cholesky factor and G^{-1}, and the
+  // contraction W^T = A^T Lhat (n x l).  When the contraction is long enough
+  // to run in several rounds of blocks, the G chain runs on the auxiliary
+  // stream beside it; a one-round contraction holds every CU and would only
+  // delay the chain (and one of its own blocks), so then the chain runs first.
+  const bool overlap = A->layout == RLU_CSR || (double)m * (double)n * (double)l >= 1e11;
+  hipStream_t gs = overlap ? ax.aux : st;
+  if (overlap) {
+    if ((e = hipEventRecord(ax.fork, st)) != hipSuccess || (e = hipStreamWaitEvent(ax.aux, ax.fork, 0)) != hipSuccess)
+      return hip_fail(e, "fork");
+  }
+  sm.begin(RLU_STAGE_GRAM, gs);
+  {
+    GemmArgs g{};
+    g.M = l; g.N = l; g.K = m;
+    g.A = Lhat; g.lda = l; g.a_dtype = RLU_F64; g.trans_a = true;
+    g.B = Lhat; g.ldb = l;
+    g.C = at<double>(ws, fp.Gm); g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
+    e = gemm_f64_splitk(g, fp.splits_g, at<double>(ws, fp.parts_g), gs);
+    if (e != hipSuccess) return hip_fail(e, "Gram matrix");
+  }
+  sm.end(RLU_STAGE_GRAM, gs);
+  sm.begin(RLU_STAGE_CHOL, gs);
+  if ((e = launch_chol_inv(l, at<double>(ws, fp.Gm), at<double>(ws, fp.Linv), at<double>(ws, fp.Dinv), info, gs)) != hipSuccess)
+    return hip_fail(e, "Cholesky");
+  {  // G^{-1} = Linv^T Linv
+    GemmArgs g{};
+    g.M = l; g.N = l; g.K = l;
+    g.A = at<double>(ws, fp.Linv); g.lda = l; g.a_dtype = RLU_F64; g.trans_a = true;
+    g.B = at<double>(ws, fp.Linv); g.ldb = l;
+    g.C = at<double>(ws, fp.Ginv); g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
+    if ((e = gemm_f64(g, gs)) != hipSuccess) return hip_fail(e, "inverse Gram");
+  }
+  sm.end(RLU_STAGE_CHOL, gs);
+  if (overlap && (e = hipEventRecord(ax.join, ax.aux)) != hipSuccess) return hip_fail(e, "join");
+
   double *Wt = at<double>(ws, fp.Wt);
-  sm.mark(RLU_STAGE_CONTRACT);
+  sm.begin(RLU_STAGE_CONTRACT, st);
   if (A->layout == RLU_CSR) {
     e = contraction_csr(m, n, l, A->row_ptr, A->col_idx, (const double *)A->values, A->nnz, Lhat, Wt,
                         at<void>(ws, fp.csc), cx.caps.num_cu, st);
@@ -262,28 +337,9 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     e = precision_contract(fp.pp, A, Lhat, l, Wt, at<double>(ws, fp.parts), fp.splits_w, at<void>(ws, fp.prec), st);
     if (e != hipSuccess) return hip_fail(e, "reduced-precision contraction");
   }
-  sm.mark(RLU_STAGE_GRAM);
-  {
-    GemmArgs g{};
-    g.M = l; g.N = l; g.K = m;
-    g.A = Lhat; g.lda = l; g.a_dtype = RLU_F64; g.trans_a = true;
-    g.B = Lhat; g.ldb = l;
-    g.C = at<double>(ws, fp.Gm); g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
-    e = gemm_f64_splitk(g, fp.splits_g, at<double>(ws, fp.parts), st);
-    if (e != hipSuccess) return hip_fail(e, "Gram matrix");
-  }
-  sm.mark(RLU_STAGE_CHOL);
-  if ((e = launch_chol_inv(l, at<double>(ws, fp.Gm), at<double>(ws, fp.Linv), at<double>(ws, fp.Dinv), info, st)) != hipSuccess)
-    return hip_fail(e, "Cholesky");
-  {  // G^{-1} = Linv^T Linv
-    GemmArgs g{};
-    g.M = l; g.N = l; g.K = l;
-    g.A = at<double>(ws, fp.Linv); g.lda = l; g.a_dtype = RLU_F64; g.trans_a = true;
-    g.B = at<double>(ws, fp.Linv); g.ldb = l;
-    g.C = at<double>(ws, fp.Ginv); g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
-    if ((e = gemm_f64(g, st)) != hipSuccess) return hip_fail(e, "inverse Gram");
-  }
-  sm.mark(RLU_STAGE_SOLVE);
+  sm.end(RLU_STAGE_CONTRACT, st);
+  if (overlap && (e = hipStreamWaitEvent(st, ax.join, 0)) != hipSuccess) return hip_fail(e, "join");
+  sm.begin(RLU_STAGE_SOLVE, st);
   if (A->layout == RLU_DENSE_ROW_MAJOR && p->precision == RLU_PREC_BF16_REFINED) {
     // one refinement step of the BF16 contraction; writes Bt
     e = precision_refine(fp.pp, A, l, Wt, at<double>(ws, fp.Ginv), at<double>(ws, fp.Bt), at<void>(ws, fp.prec), st);
@@ -296,6 +352,7 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     g.C = at<double>(ws, fp.Bt); g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
     if ((e = gemm_f64(g, st)) != hipSuccess) return hip_fail(e, "least-squares product");
   }
+  sm.end(RLU_STAGE_SOLVE, st);
   double *Bt = at<double>(ws, fp.Bt);
   if (out->B) {
     if ((e = launch_transpose(n, l, Bt, l, out->B, n, st)) != hipSuccess) return hip_fail(e, "transpose");
@@ -303,11 +360,12 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
 
   // Step 5: B Q = L~ U through the row-pivoted LU of B^T
   double *Lph = at<double>(ws, fp.Lph), *Up = at<double>(ws, fp.Up), *Lt = at<double>(ws, fp.Lt);
-  sm.mark(RLU_STAGE_LU_B);
+  sm.begin(RLU_STAGE_LU_B, st);
   e = launch_gepp(n, l, Bt, l, Lph, Up, out->perm_c, out->ipiv_c, at<void>(ws, fp.slots), abort_flag, info, 1,
                   fp.pb, st);
   if (e != hipSuccess) return hip_fail(e, "column-pivoted LU launch");
-  sm.mark(RLU_STAGE_ASSEMBLE);
+  sm.end(RLU_STAGE_LU_B, st);
+  sm.begin(RLU_STAGE_ASSEMBLE, st);
   if ((e = launch_ltilde(l, Up, Lt, st)) != hipSuccess) return hip_fail(e, "L~");
   if ((e = launch_assemble_u(l, n, Up, Lph, out->perm_c, out->U, out->ldu, st)) != hipSuccess)
     return hip_fail(e, "U");
@@ -322,7 +380,7 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     if ((e = gemm_f64(g, st)) != hipSuccess) return hip_fail(e, "L = L_y L~");
   }
   if ((e = launch_finalize(info, abort_flag, st)) != hipSuccess) return hip_fail(e, "finalize");
-  sm.mark(RLU_NUM_STAGES);
+  sm.end(RLU_STAGE_ASSEMBLE, st);
   return RLU_OK;
 }
 
@@ -367,6 +425,7 @@ rlu_status rlu_destroy(rlu_ctx *ctx) {
   if (!ctx) return RLU_OK;
   rlu_ctx_impl *c = reinterpret_cast<rlu_ctx_impl *>(ctx);
   serve_shutdown(*c);
+  destroy_aux_streams(*c);
   for (hipEvent_t e : c->timer.pool) hipEventDestroy(e);
   delete c;
   return RLU_OK;
@@ -441,11 +500,11 @@ rlu_status rlu_stage_times(rlu_ctx *ctx, float *ms, int *calls) {
   for (int i = 0; i < RLU_NUM_STAGES; ++i) ms[i] = 0.f;
   StageTimer &t = cx.timer;
   for (auto &ev : t.calls) {
-    hipError_t e = hipEventSynchronize(ev[RLU_NUM_STAGES]);
-    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
     for (int i = 0; i < RLU_NUM_STAGES; ++i) {
+      hipError_t e = hipEventSynchronize(ev[2 * i + 1]);
+      if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
       float v = 0.f;
-      if ((e = hipEventElapsedTime(&v, ev[i], ev[i + 1])) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+      if ((e = hipEventElapsedTime(&v, ev[2 * i], ev[2 * i + 1])) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
       ms[i] += v;
     }
   }

@@ -24,12 +24,22 @@ __device__ inline double2 cmul(double2 a, double2 w) {
   return make_double2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
 }
 
+// Powers w^e (0 <= e < N) of a root of unity from two small LDS tables:
+// w^e = lo[e mod 2^b] * hi[e >> b], with lo[i] = w^i and hi[i] = w^(i 2^b).
+// The product of two correctly rounded unit values is within a few ulp of
+// w^e.  Keeps the transform free of global loads, so loads issued before it
+// (the next row's prefetch) are not waited for inside it.
+struct TwSplit {
+  const double2 *lo, *hi;
+  int b, mask;
+  __device__ inline double2 operator()(int e) const { return cmul(lo[e & mask], hi[e >> b]); }
+};
+
 // In: x (N complex, LDS).  Uses y (N complex, LDS) as the other ping-pong
 // buffer.  Returns the buffer that holds the spectrum.  Must be called by
 // every thread of the block; ends with a block barrier.
-template <int THREADS>
-__device__ inline double2 *fft_lds(double2 *x, double2 *y, int N, int log2N,
-                                   const double2 *__restrict__ twf) {
+template <int THREADS, typename TW>
+__device__ inline double2 *fft_lds(double2 *x, double2 *y, int N, int log2N, const TW &twf) {
   const int tid = threadIdx.x;
   int Ns = 1;
   if (log2N & 1) {
@@ -51,9 +61,9 @@ __device__ inline double2 *fft_lds(double2 *x, double2 *y, int N, int log2N,
       double2 v0 = x[j], v1 = x[j + N4], v2 = x[j + 2 * N4], v3 = x[j + 3 * N4];
       if (Ns > 1) {
         const int e = k * tstep;
-        v1 = cmul(v1, twf[e]);
-        v2 = cmul(v2, twf[2 * e]);
-        v3 = cmul(v3, twf[3 * e]);
+        v1 = cmul(v1, twf(e));
+        v2 = cmul(v2, twf(2 * e));
+        v3 = cmul(v3, twf(3 * e));
       }
       const double2 a0 = cadd(v0, v2), a1 = csub(v0, v2), a2 = cadd(v1, v3);
       const double2 d3 = csub(v1, v3);
@@ -72,9 +82,9 @@ __device__ inline double2 *fft_lds(double2 *x, double2 *y, int N, int log2N,
 }
 
 // Coordinate f (0 <= f < s) of the orthonormal real transform, from the
-// packed spectrum Z (N = s/2 complex values).
-__device__ inline double real_coord(const double2 *Z, int s, int f,
-                                    const double2 *__restrict__ twp, double rs, double r2s) {
+// packed spectrum Z (N = s/2 complex values); twp(g) = exp(-2 pi i g / s).
+template <typename TW>
+__device__ inline double real_coord(const double2 *Z, int s, int f, const TW &twp, double rs, double r2s) {
   const int N = s >> 1;
   if (f == 0) { const double2 z0 = Z[0]; return (z0.x + z0.y) * rs; }
   if (f == N) { const double2 z0 = Z[0]; return (z0.x - z0.y) * rs; }
@@ -82,7 +92,7 @@ __device__ inline double real_coord(const double2 *Z, int s, int f,
   const double2 zg = Z[g], zn = Z[N - g];
   const double er = 0.5 * (zg.x + zn.x), ei = 0.5 * (zg.y - zn.y);
   const double orr = 0.5 * (zg.y + zn.y), oi = -0.5 * (zg.x - zn.x);
-  const double2 w = twp[g];
+  const double2 w = twp(g);
   if (f < N) return (er + (w.x * orr - w.y * oi)) * r2s;
   return (ei + (w.x * oi + w.y * orr)) * r2s;
 }

@@ -53,17 +53,54 @@ struct GeppKArgs {
   int which;
 };
 
-__device__ inline Cand block_argmax(Cand c, Cand *s_red) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  c = wave_argmax(c);
-  if (lane == 0) s_red[wave] = c;
-  __syncthreads();
-  Cand b = s_red[0];
-#pragma unroll
-  for (int w = 1; w < kGeppThreads / 64; ++w)
-    if (cand_better(s_red[w].v, s_red[w].pos, b.v, b.pos)) b = s_red[w];
-  __syncthreads();
-  return b;
+// ---- arg-max across a wave with DPP --------------------------------------------
+// The candidate order (larger |value|, then smaller position) is total on
+// real candidates, so any reduction order gives the same winner.
+template <int CTRL>
+__device__ inline int dpp_mov(int v) { return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false); }
+
+template <int CTRL>
+__device__ inline Cand cand_dpp(const Cand &c) {
+  const long long bits = __double_as_longlong(c.v);
+  const int lo = dpp_mov<CTRL>((int)bits), hi = dpp_mov<CTRL>((int)(bits >> 32));
+  Cand o;
+  o.v = __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+  o.pos = dpp_mov<CTRL>(c.pos);
+  o.idx = dpp_mov<CTRL>(c.idx);
+  return o;
+}
+__device__ inline Cand cand_lane(const Cand &c, int src) {
+  const long long bits = __double_as_longlong(c.v);
+  const int lo = __builtin_amdgcn_readlane((int)bits, src), hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
+  Cand o;
+  o.v = __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+  o.pos = __builtin_amdgcn_readlane(c.pos, src);
+  o.idx = __builtin_amdgcn_readlane(c.idx, src);
+  return o;
+}
+__device__ inline Cand cand_max(const Cand &a, const Cand &b) {  // field-wise selects keep it in registers
+  const bool t = cand_better(b.v, b.pos, a.v, a.pos);
+  Cand r;
+  r.v = t ? b.v : a.v;
+  r.pos = t ? b.pos : a.pos;
+  r.idx = t ? b.idx : a.idx;
+  return r;
+}
+
+// Winner of the wave's 64 candidates, in every lane: exchanges within quads
+// (quad_perm [1,0,3,2], [2,3,0,1]) and 16-lane rows (row_half_mirror,
+// row_mirror) by DPP, then the four row results by readlane.  Must be called
+// with all lanes active.
+__device__ inline Cand wave_argmax_dpp(Cand c) {
+  c = cand_max(c, cand_dpp<0xB1>(c));
+  c = cand_max(c, cand_dpp<0x4E>(c));
+  c = cand_max(c, cand_dpp<0x141>(c));
+  c = cand_max(c, cand_dpp<0x140>(c));
+  Cand r = cand_lane(c, 0);
+  r = cand_max(r, cand_lane(c, 16));
+  r = cand_max(r, cand_lane(c, 32));
+  r = cand_max(r, cand_lane(c, 48));
+  return r;
 }
 
 __device__ inline double pivot_mag(double v) {
@@ -71,17 +108,13 @@ __device__ inline double pivot_mag(double v) {
   return (a == a && a <= 1.7976931348623157e308) ? a : -1.0;  // non-finite -> -1
 }
 
-// Publish a candidate held in LDS (vals): values and header, all tagged.
-__device__ inline void publish(uint64_t *sl, const Cand &c, int row, const double *vals, int nbp,
-                               uint32_t tag) {
-  for (int cc = threadIdx.x; cc < nbp; cc += kGeppThreads) tw_put_f64(sl + kHdrWords + 2 * cc, vals[cc], tag);
-  if (threadIdx.x == 0) {
-    const uint64_t b = (uint64_t)__double_as_longlong(c.v);
-    tw_put(sl + 0, (uint32_t)b, tag);
-    tw_put(sl + 1, (uint32_t)(b >> 32), tag);
-    tw_put(sl + 2, (uint32_t)c.pos, tag);
-    tw_put(sl + 3, (uint32_t)row, tag);
-  }
+// Header of a published candidate: |value| (two words), position, row.
+__device__ inline void put_header(uint64_t *sl, const Cand &c, int row, uint32_t tag) {
+  const uint64_t b = (uint64_t)__double_as_longlong(c.v);
+  tw_put(sl + 0, (uint32_t)b, tag);
+  tw_put(sl + 1, (uint32_t)(b >> 32), tag);
+  tw_put(sl + 2, (uint32_t)c.pos, tag);
+  tw_put(sl + 3, (uint32_t)row, tag);
 }
 
 // Block-wide copy of `total` values into LDS: load(e) -> dst(e), with eight
@@ -107,11 +140,16 @@ __device__ inline void block_copy(int total, LoadF load, StoreF store) {
 
 template <int RPT, int NB>
 __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
-  __shared__ Cand s_red[kGeppThreads / 64];
-  __shared__ Cand s_win;
-  __shared__ int s_wrow, s_zero, s_nonfinite, s_ok;
-  __shared__ double pvs[2 * NB];   // winner's row, shifted: pvs[k] = column j + k (zero padded)
-  __shared__ double cvals[NB];     // this block's candidate row, shifted the same way
+  constexpr int NW = kGeppThreads / 64;
+  // per-step state, double-buffered by step parity so that two block
+  // barriers per step suffice (see the step loop)
+  __shared__ Cand s_red[2][NW];
+  __shared__ Cand s_win[2];
+  __shared__ int s_wrow[2], s_ok[2];
+  __shared__ int s_zero, s_nonfinite;
+  __shared__ double pvs[2][2 * NB];  // winner's row, shifted: pvs[p][k] = column j + k (zero padded)
+  __shared__ double cvals[NW][NB];   // each wave's best candidate row (before this step's update), staged
+  __shared__ double cmlt[NW];        // and its multiplier of this step
 
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -128,7 +166,7 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
   int64_t row[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    const int li = tid + kGeppThreads * q;
+    const int li = tid + kGeppThreads * q;  // row of the block; candidates carry it as their idx
     const bool owned = li < a.R && r0 + li < M;
     row[q] = owned ? r0 + li : -1;  // -1 never matches a winner's row
     pos[q] = owned ? (j0 == 0 ? (int)row[q] : a.posg[row[q]]) : -1;  // -1: no row
@@ -140,6 +178,52 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
 #pragma unroll
     for (int k = 0; k < NB; ++k) x[q][k] = (live && k < nbp) ? a.X[row[q] * a.ldx + j0 + k] : 0.0;
   }
+
+  // Block arg-max of the threads' candidates with one barrier: each wave's
+  // winning lane stages its row in that wave's LDS slot before the barrier;
+  // after it, wave 0 publishes the block's winner (tagged values, then the
+  // header) and only then goes on to poll, so a block's own publication is
+  // never held up behind its polling.
+  // The staged row is the candidate's row before this step's update, with
+  // its multiplier; with pv != nullptr wave 0's lanes apply the update
+  // (x[k + 1] - mlt pv[k + 1]) while publishing, which the block's other rows
+  // get only afterwards.
+  auto propose = [&](const Cand &cand, int owner_q, int par, uint64_t *sl, int nvals, uint32_t tag,
+                     const double *pv, const double *mltq) __attribute__((always_inline)) {
+    const Cand wb = wave_argmax_dpp(cand);
+    if (wb.idx >= 0 && tid == wb.idx % kGeppThreads) {  // this lane won its wave: stage row owner_q
+      double rv[NB];
+      double mo = mltq ? mltq[0] : 0.0;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) rv[k] = x[0][k];
+#pragma unroll
+      for (int q = 1; q < RPT; ++q) {
+        const bool take = (q == owner_q);
+        if (mltq) mo = take ? mltq[q] : mo;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) rv[k] = take ? x[q][k] : rv[k];
+      }
+#pragma unroll
+      for (int k = 0; k < NB; ++k) cvals[wave][k] = rv[k];
+      cmlt[wave] = mo;
+    }
+    if (lane == 0) s_red[par][wave] = wb;
+    __syncthreads();
+    if (wave == 0) {
+      Cand best = s_red[par][0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) best = cand_max(best, s_red[par][w]);
+      if (best.idx >= 0) {
+        const int bw = (best.idx % kGeppThreads) / 64;
+        const double *cv = cvals[bw];
+        const double mo = cmlt[bw];
+        for (int cc = lane; cc < nvals; cc += 64)
+          tw_put_f64(sl + kHdrWords + 2 * cc, pv ? cv[cc + 1] - mo * pv[cc + 1] : cv[cc], tag);
+      }
+      if (lane == 0) put_header(sl, best, best.idx >= 0 ? (int)(r0 + best.idx) : -1, tag);
+    }
+  };
+
   {  // candidate for the panel's first column
     Cand cand{-2.0, 0x7fffffff, -1};
     int owner_q = 0;
@@ -150,21 +234,17 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
         if (cand_better(av, pos[q], cand.v, cand.pos)) { cand = Cand{av, pos[q], tid + kGeppThreads * q}; owner_q = q; }
       }
     }
-    const Cand best = block_argmax(cand, s_red);
-    if (best.idx >= 0 && best.idx == cand.idx) {
-#pragma unroll
-      for (int q = 0; q < RPT; ++q)
-        if (q == owner_q)
-#pragma unroll
-          for (int k = 0; k < NB; ++k) cvals[k] = x[q][k];
-    }
-    __syncthreads();
-    uint64_t *sl = a.slots + ((size_t)(j0 & 1) * G + g) * a.SSW;
-    publish(sl, best, best.idx >= 0 ? (int)(r0 + best.idx) : -1, cvals, nbp, (uint32_t)(j0 + 1));
+    propose(cand, owner_q, 1, a.slots + ((size_t)(j0 & 1) * G + g) * a.SSW, nbp, (uint32_t)(j0 + 1), nullptr,
+            nullptr);
   }
 
+  // Step c uses buffers [c & 1]: wave 0 fills them before barrier S1(c); the
+  // other waves read them after S1(c); the next writes to the same buffers
+  // come at step c + 2, after every wave has passed S1(c + 1), hence done
+  // with step c.  S2(c) is the barrier inside propose; cvals is rewritten at
+  // step c + 1 only after S1(c + 1), which wave 0 reaches after publishing.
   for (int c = 0; c < nbp; ++c) {
-    const int j = j0 + c;
+    const int j = j0 + c, par = c & 1;
     const int rem = nbp - c;  // columns j .. j1-1 still in the panel
     const uint32_t tag = (uint32_t)(j + 1);
     const uint64_t *slp = a.slots + (size_t)(j & 1) * G * a.SSW;
@@ -176,9 +256,9 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
         int ready = 1;
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
-          const int s = lane + 64 * qq;
-          if (s < G) {
-            const uint64_t *sl = slp + (size_t)s * a.SSW;
+          const int sidx = lane + 64 * qq;
+          if (sidx < G) {
+            const uint64_t *sl = slp + (size_t)sidx * a.SSW;
             h0[qq] = tw_get(sl);
             h1[qq] = tw_get(sl + 1);
             h2[qq] = tw_get(sl + 2);
@@ -191,14 +271,14 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
       Cand best{-3.0, 0x7fffffff, -1};
 #pragma unroll
       for (int qq = 0; qq < 4; ++qq) {
-        const int s = lane + 64 * qq;
-        if (s < G) {
+        const int sidx = lane + 64 * qq;
+        if (sidx < G) {
           const double v = tw_f64(h0[qq], h1[qq]);
           const int p = (int)tw_data(h2[qq]);
-          if (cand_better(v, p, best.v, best.pos)) best = Cand{v, p, s};
+          if (cand_better(v, p, best.v, best.pos)) best = Cand{v, p, sidx};
         }
       }
-      best = wave_argmax(best);
+      best = wave_argmax_dpp(best);
       ok = __all(ok);
       // the winner's (shifted) panel row and row index, read by the same wave
       if (ok) {
@@ -215,7 +295,7 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
             }
             v = tw_f64(lo, hi);
           }
-          pvs[k] = v;
+          pvs[par][k] = v;
         }
         if (lane == 0) {
           uint64_t w3;
@@ -224,18 +304,56 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
             if (tw_tag(w3) == tag) break;
             if ((it & 255) == 0 && !poll_ok(t0, tmo, a.abort_flag)) { ok = 0; break; }
           }
-          s_wrow = (int)tw_data(w3);
+          s_wrow[par] = (int)tw_data(w3);
         }
         ok = __all(ok);
       }
-      if (lane == 0) { s_win = best; s_ok = ok; }
+      if (lane == 0) { s_win[par] = best; s_ok[par] = ok; }
     }
-    __syncthreads();
-    if (!s_ok) return;
-    const Cand win = s_win;
-    const int wrow = s_wrow, wpos = win.pos;
+    __syncthreads();  // S1(c)
+    if (!s_ok[par]) return;
+    const Cand win = s_win[par];
+    const int wrow = s_wrow[par], wpos = win.pos;
     const bool zero = !(win.v > 0.0);
-    const double piv = pvs[0];
+    const double *pv = pvs[par];
+    const double piv = pv[0];
+
+    // positions and multipliers; column j + 1 of every live row first (the
+    // next step's candidates), the rest of the shifted update after this
+    // block's candidate is published
+    const bool next = (c + 1 < nbp);
+    Cand cand{-2.0, 0x7fffffff, -1};
+    int owner_q = 0, nonfinite = 0;
+    double mltq[RPT], x1[RPT];
+    bool live[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      if (row[q] == wrow) pos[q] = j;
+      else if (pos[q] == j) pos[q] = wpos;
+      live[q] = pos[q] > j;
+      mltq[q] = (live[q] && !zero) ? x[q][0] / piv : 0.0;
+      x1[q] = x[q][1] - mltq[q] * pv[1];
+      if (live[q]) {
+        a.Lhat[row[q] * l + j] = mltq[q];
+        if (next) {
+          const double av = pivot_mag(x1[q]);
+          nonfinite += (av < 0.0);
+          if (cand_better(av, pos[q], cand.v, cand.pos)) { cand = Cand{av, pos[q], tid + kGeppThreads * q}; owner_q = q; }
+        }
+      }
+    }
+    if (next)
+      propose(cand, owner_q, par, a.slots + ((size_t)((j + 1) & 1) * G + g) * a.SSW, rem - 1, tag + 1, pv, mltq);
+    if (nonfinite) atomicAdd(&s_nonfinite, nonfinite);
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      if (live[q]) {
+        x[q][0] = x1[q];
+#pragma clang loop unroll(full)
+        for (int k = 1; k + 1 < NB; ++k) x[q][k] = x[q][k + 1] - mltq[q] * pv[k + 1];
+        x[q][NB - 1] = 0.0;
+      }
+    }
     if (g == 0) {
       if (tid == 0) {
         if (a.ipiv) a.ipiv[j] = wpos;
@@ -243,45 +361,8 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
         if (zero) ++s_zero;
       }
       double *urow = a.U + (size_t)j * l;
-      for (int cc = tid; cc < j1; cc += kGeppThreads) urow[cc] = (cc < j) ? 0.0 : pvs[cc - j];
+      for (int cc = tid; cc < j1; cc += kGeppThreads) urow[cc] = (cc < j) ? 0.0 : pv[cc - j];
     }
-
-    // positions, multipliers, and the shifted update of the whole panel
-    const bool next = (c + 1 < nbp);
-    Cand cand{-2.0, 0x7fffffff, -1};
-    int owner_q = 0, nonfinite = 0;
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      if (row[q] == wrow) pos[q] = j;
-      else if (pos[q] == j) pos[q] = wpos;
-      if (pos[q] > j) {
-        const double mlt = zero ? 0.0 : x[q][0] / piv;
-        a.Lhat[row[q] * l + j] = mlt;
-#pragma clang loop unroll(full)
-        for (int k = 0; k + 1 < NB; ++k) x[q][k] = x[q][k + 1] - mlt * pvs[k + 1];
-        x[q][NB - 1] = 0.0;
-        if (next) {
-          const double av = pivot_mag(x[q][0]);
-          nonfinite += (av < 0.0);
-          if (cand_better(av, pos[q], cand.v, cand.pos)) { cand = Cand{av, pos[q], tid + kGeppThreads * q}; owner_q = q; }
-        }
-      }
-    }
-    if (nonfinite) atomicAdd(&s_nonfinite, nonfinite);
-    if (next) {
-      const Cand best = block_argmax(cand, s_red);
-      if (best.idx >= 0 && best.idx == cand.idx) {
-#pragma unroll
-        for (int q = 0; q < RPT; ++q)
-          if (q == owner_q)
-#pragma unroll
-            for (int k = 0; k < NB; ++k) cvals[k] = x[q][k];
-      }
-      __syncthreads();
-      uint64_t *sl = a.slots + ((size_t)((j + 1) & 1) * G + g) * a.SSW;
-      publish(sl, best, best.idx >= 0 ? (int)(r0 + best.idx) : -1, cvals, rem - 1, tag + 1);
-    }
-    __syncthreads();
   }
 
   // L entries of rows pivoted in this panel or before: 1 on the pivot, 0
@@ -367,8 +448,8 @@ static GeppKernel gepp_kernel(int rpt) {
 bool plan_gepp(int64_t rows, int cols, const DevCaps &caps, GeppPlan *plan, std::string *why) {
   if (rows < cols || cols < 1) { *why = "tall LU needs rows >= cols >= 1"; return false; }
   const int gmax = std::min(256, std::max(1, caps.num_cu));
-  // ~256 rows per block (one per thread), and few enough blocks that the
-  // all-to-all header exchange stays cheap.
+  // about one row per thread where possible, and few enough blocks that the
+  // all-to-all exchange stays cheap
   int64_t G = std::min<int64_t>(gmax, std::max<int64_t>(1, ceil_div(rows, kGeppThreads)));
   int64_t R = ceil_div(rows, G);
   G = ceil_div(rows, R);

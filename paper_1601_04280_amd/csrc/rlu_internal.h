@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <array>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -134,16 +135,26 @@ hipError_t launch_finalize(rlu_info *info, const int32_t *abort_flag, hipStream_
 
 // ---- context, errors, validation ---------------------------------------------------
 struct ServeState;
-// HIP events of stage boundaries for calls made with RLU_FLAG_TIMING.
+// HIP events (start, end) of every stage for calls made with RLU_FLAG_TIMING.
+// Stages on the auxiliary stream overlap the contraction.
 struct StageTimer {
   std::vector<hipEvent_t> pool;
   size_t used = 0;
-  std::vector<std::array<hipEvent_t, RLU_NUM_STAGES + 1>> calls;
+  std::vector<std::array<hipEvent_t, 2 * RLU_NUM_STAGES>> calls;
+};
+// A second stream per caller stream: the Gram matrix, its Cholesky factor and
+// G^{-1} depend only on Lhat and run there while the contraction runs on the
+// caller's stream (fork and join through the two events).
+struct AuxStream {
+  hipStream_t main = nullptr, aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 struct rlu_ctx_impl {
   DevCaps caps{};
   ServeState *serve = nullptr;
   StageTimer timer;
+  std::mutex aux_mu;
+  std::vector<AuxStream> aux;
 };
 rlu_status fail(rlu_status st, const char *fmt, ...);
 rlu_status hip_fail(hipError_t e, const char *what);
@@ -160,8 +171,8 @@ struct FactorPlan {
   int splits_w, splits_g;
   PrecPlan pp;
   // offsets (bytes) into the workspace
-  size_t ctl, code, sel, twf, twp, Y, slots, csc, Lhat, Uy, Wt, parts, Gm, Linv, Dinv, Ginv, Bt, Lph,
-      Up, Lt, prec;
+  size_t ctl, code, sel, twf, twp, Y, slots, csc, Lhat, Uy, Wt, parts, parts_g, Gm, Linv, Dinv, Ginv, Bt,
+      Lph, Up, Lt, prec;
   size_t total;
   size_t sketch_total;
 };

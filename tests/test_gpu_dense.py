@@ -98,6 +98,19 @@ def test_tall_lu_matches_oracle(rows, cols, seed):
     assert int(info[1].item()) == zp == 0
 
 
+@pytest.mark.parametrize("rows,cols,seed", [(120000, 40, 5), (200000, 24, 6)])
+def test_tall_lu_very_tall(rows, cols, seed):
+    """Several rows per thread (two and four) and a panel narrower than the
+    matrix."""
+    y, (L, U, perm, ipiv, zp, gap) = screened_gaussian(rows, cols, seed)
+    Lhat, Ug, permg, ipivg, info = rlu.tall_lu(to_dev(y))
+    np.testing.assert_array_equal(ipivg.cpu().numpy(), ipiv)
+    np.testing.assert_array_equal(permg.cpu().numpy(), perm)
+    Lg = Lhat.cpu().numpy()[perm]
+    np.testing.assert_allclose(Lg, L, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(Ug.cpu().numpy(), U, rtol=0, atol=1e-12 * np.abs(U).max())
+
+
 def test_tall_lu_zero_columns():
     # pivot -64 (a power of two) makes every multiplier and product exact, so
     # the Schur column 3 (= 2 x column 0) is exactly zero on both sides
