@@ -57,7 +57,7 @@ struct GeppKArgs {
 // The candidate order (larger |value|, then smaller position) is total on
 // real candidates, so any reduction order gives the same winner.
 template <int CTRL>
-__device__ inline int dpp_mov(int v) { return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false); }
+__device__ inline int dpp_mov(int v) { return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false); }
 
 template <int CTRL>
 __device__ inline Cand cand_dpp(const Cand &c) {
@@ -141,6 +141,7 @@ __device__ inline void block_copy(int total, LoadF load, StoreF store) {
 template <int RPT, int NB>
 __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
   constexpr int NW = kGeppThreads / 64;
+  constexpr int kKG = NB < 8 ? NB : 8;  // column group of the uniform skips
   // per-step state, double-buffered by step parity so that two block
   // barriers per step suffice (see the step loop)
   __shared__ Cand s_red[2][NW];
@@ -203,23 +204,44 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
 #pragma unroll
         for (int k = 0; k < NB; ++k) rv[k] = take ? x[q][k] : rv[k];
       }
+      // only the values the publication reads (indices up to nvals), in
+      // groups of kKG under a uniform branch
 #pragma unroll
-      for (int k = 0; k < NB; ++k) cvals[wave][k] = rv[k];
+      for (int g0 = 0; g0 < NB; g0 += kKG)
+        if (g0 <= nvals) {
+#pragma unroll
+          for (int k = g0; k < g0 + kKG; ++k) cvals[wave][k] = rv[k];
+        }
       cmlt[wave] = mo;
     }
     if (lane == 0) s_red[par][wave] = wb;
     __syncthreads();
     if (wave == 0) {
-      Cand best = s_red[par][0];
+      // one round of LDS reads: every wave's winner, staged value and
+      // multiplier for this lane's column (nvals <= NB <= 64: one per lane);
+      // the block's winner then selects among them in registers
+      const int ci = min(lane + (pv ? 1 : 0), NB - 1);
+      Cand r[NW];
+      double cvw[NW], mow[NW];
 #pragma unroll
-      for (int w = 1; w < NW; ++w) best = cand_max(best, s_red[par][w]);
-      if (best.idx >= 0) {
-        const int bw = (best.idx % kGeppThreads) / 64;
-        const double *cv = cvals[bw];
-        const double mo = cmlt[bw];
-        for (int cc = lane; cc < nvals; cc += 64)
-          tw_put_f64(sl + kHdrWords + 2 * cc, pv ? cv[cc + 1] - mo * pv[cc + 1] : cv[cc], tag);
+      for (int w = 0; w < NW; ++w) {
+        r[w] = s_red[par][w];
+        cvw[w] = cvals[w][ci];
+        mow[w] = cmlt[w];
       }
+      const double pvc = pv ? pv[ci] : 0.0;
+      Cand best = r[0];
+      double cv = cvw[0], mo = mow[0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) {
+        const bool t = cand_better(r[w].v, r[w].pos, best.v, best.pos);
+        best.v = t ? r[w].v : best.v;
+        best.pos = t ? r[w].pos : best.pos;
+        best.idx = t ? r[w].idx : best.idx;
+        cv = t ? cvw[w] : cv;
+        mo = t ? mow[w] : mo;
+      }
+      if (best.idx >= 0 && lane < nvals) tw_put_f64(sl + kHdrWords + 2 * lane, pv ? cv - mo * pvc : cv, tag);
       if (lane == 0) put_header(sl, best, best.idx >= 0 ? (int)(r0 + best.idx) : -1, tag);
     }
   };
@@ -250,7 +272,7 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
     const uint64_t *slp = a.slots + (size_t)(j & 1) * G * a.SSW;
     if (wave == 0) {  // all headers of step j -> winner (G <= 256: <= 4 slots per lane)
       const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-      uint64_t h0[4], h1[4], h2[4];
+      uint64_t h0[4], h1[4], h2[4], h3[4] = {0, 0, 0, 0};
       int ok = 1;
       for (uint32_t it = 1;; ++it) {
         int ready = 1;
@@ -262,7 +284,9 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
             h0[qq] = tw_get(sl);
             h1[qq] = tw_get(sl + 1);
             h2[qq] = tw_get(sl + 2);
-            ready &= (tw_tag(h0[qq]) == tag) & (tw_tag(h1[qq]) == tag) & (tw_tag(h2[qq]) == tag);
+            h3[qq] = tw_get(sl + 3);
+            ready &= (tw_tag(h0[qq]) == tag) & (tw_tag(h1[qq]) == tag) & (tw_tag(h2[qq]) == tag) &
+                     (tw_tag(h3[qq]) == tag);
           }
         }
         if (__all(ready)) break;
@@ -280,32 +304,30 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
       }
       best = wave_argmax_dpp(best);
       ok = __all(ok);
-      // the winner's (shifted) panel row and row index, read by the same wave
+      // the winner's row index (header word 3, already read by the lane that
+      // polled its slot) and its shifted panel row, one value per lane
+      // (rem <= NB <= 64), in a single round of loads
       if (ok) {
+        const int wq = best.idx >> 6;
+        uint64_t hw = h3[0];
+#pragma unroll
+        for (int qq = 1; qq < 4; ++qq) hw = (qq == wq) ? h3[qq] : hw;
+        const int wrow_read = __builtin_amdgcn_readlane((int)tw_data(hw), best.idx & 63);
         const uint64_t *wsl = slp + (size_t)best.idx * a.SSW;
-        for (int k = lane; k < 2 * NB; k += 64) {
-          double v = 0.0;
-          if (k < rem) {
-            uint64_t lo, hi;
-            for (uint32_t it = 1;; ++it) {
-              lo = tw_get(wsl + kHdrWords + 2 * k);
-              hi = tw_get(wsl + kHdrWords + 2 * k + 1);
-              if (tw_tag(lo) == tag && tw_tag(hi) == tag) break;
-              if ((it & 255) == 0 && !poll_ok(t0, tmo, a.abort_flag)) { ok = 0; break; }
-            }
-            v = tw_f64(lo, hi);
-          }
-          pvs[par][k] = v;
-        }
-        if (lane == 0) {
-          uint64_t w3;
+        double v = 0.0;
+        if (lane < rem) {
+          uint64_t lo, hi;
           for (uint32_t it = 1;; ++it) {
-            w3 = tw_get(wsl + 3);
-            if (tw_tag(w3) == tag) break;
+            lo = tw_get(wsl + kHdrWords + 2 * lane);
+            hi = tw_get(wsl + kHdrWords + 2 * lane + 1);
+            if (tw_tag(lo) == tag && tw_tag(hi) == tag) break;
             if ((it & 255) == 0 && !poll_ok(t0, tmo, a.abort_flag)) { ok = 0; break; }
           }
-          s_wrow[par] = (int)tw_data(w3);
+          v = tw_f64(lo, hi);
         }
+#pragma unroll
+        for (int k = lane; k < 2 * NB; k += 64) pvs[par][k] = (k == lane) ? v : 0.0;
+        if (lane == 0) s_wrow[par] = wrow_read;
         ok = __all(ok);
       }
       if (lane == 0) { s_win[par] = best; s_ok[par] = ok; }
@@ -349,9 +371,15 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
     for (int q = 0; q < RPT; ++q) {
       if (live[q]) {
         x[q][0] = x1[q];
-#pragma clang loop unroll(full)
-        for (int k = 1; k + 1 < NB; ++k) x[q][k] = x[q][k + 1] - mltq[q] * pv[k + 1];
-        x[q][NB - 1] = 0.0;
+        // columns from rem on are zero and stay zero (pv is zero padded):
+        // whole groups of kKG columns past rem are skipped (uniform branch)
+#pragma unroll
+        for (int g0 = 0; g0 < NB; g0 += kKG) {
+          if (g0 < rem) {
+#pragma unroll
+            for (int k = (g0 ? g0 : 1); k < g0 + kKG; ++k) x[q][k] = (k + 1 < NB) ? x[q][k + 1] - mltq[q] * pv[k + 1] : 0.0;
+          }
+        }
       }
     }
     if (g == 0) {

@@ -119,7 +119,8 @@ struct Cand {
 };
 
 __device__ inline bool cand_better(double v1, int p1, double v2, int p2) {
-  return (v1 > v2) || (v1 == v2 && p1 < p2);
+  // bitwise, so that it compiles to straight-line compares and mask logic
+  return (v1 > v2) | ((v1 == v2) & (p1 < p2));
 }
 
 __device__ inline Cand wave_argmax(Cand c) {
