@@ -169,7 +169,7 @@ static rlu_status run_sketch(const rlu_ctx_impl &cx, const FactorPlan &fp, const
   if (A->layout == RLU_DENSE_ROW_MAJOR) {
     e = launch_sketch_dense(A->m, A->n, A->values, A->dtype, A->ld, p->s, p->l, at<uint32_t>(ws, fp.code),
                             at<int32_t>(ws, fp.sel), at<double2>(ws, fp.twf), at<double2>(ws, fp.twp),
-                            Y, ldy, cx.caps.num_cu, st);
+                            Y, ldy, at<uint32_t>(ws, fp.ctl) + 3, cx.caps.num_cu, st);
   } else {
     if (info) {
       e = launch_csr_check(A, (p->flags & RLU_FLAG_VALIDATE) != 0, info, st);
@@ -473,6 +473,7 @@ rlu_status rlu_sketch(rlu_ctx *ctx, const rlu_matrix *A, const rlu_params *p, do
   hipError_t e = hipSetDevice(cx.caps.device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if ((e = launch_fill_u32(at<uint32_t>(ws, fp.ctl), 0u, kCtlWords, s)) != hipSuccess) return hip_fail(e, "fill");
   if ((st = run_params(fp, p, ws, s)) != RLU_OK) return st;
   return run_sketch(cx, fp, A, p, Y, ldy, ws, nullptr, s);
 }

@@ -102,6 +102,331 @@ __global__ __launch_bounds__(kSketchThreads) void k_sketch_dense(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Wave-specialised form (s <= 2048, aligned rows whose length is a multiple of
+// the vector width): blocks of four waves, four blocks per CU.  Three waves
+// stream row r with 16-byte loads, a chunk of the row in flight per thread,
+// and scatter it into LDS buffer r & 1; the fourth meanwhile transforms row
+// r - 1 in the other buffer,
+// writes its l coordinates and clears the buffer.  One block barrier per row,
+// and the transform (by one wave, in place, decimation in frequency, with
+// the split twiddle tables in LDS) is off the row stream's critical path.
+// Complex index i is stored at i + i / 16 (one pad per 16) so that the
+// passes' strided accesses spread over the LDS banks.
+constexpr int kWsSem = 192;                 // streaming threads (three waves)
+constexpr int kWsThreads = kWsSem + 64;     // plus the transform wave: one wave per SIMD
+constexpr int kWsMaxN = 1024;               // complex length (s <= 2048)
+
+__host__ __device__ inline int padc(int i) { return i + (i >> 4); }
+
+// In-place decimation-in-frequency transform of N <= 1024 complex values by
+// one wave (kernel e^{-2 pi i / N}).  Passes of radix 16 while the block size
+// M is at least 16, then radix 4, or radix 2 then 4, or 2, for what is left
+// (1024 = 16 16 4).  A pass of radix R over blocks of size M = R S computes,
+// for each block start g and 0 <= j < S, from a_r = z[g + j + r S]:
+//   y_m = (sum_r a_r e^{-2 pi i r m / R}) w^{j m},  w = e^{-2 pi i / M},
+// and stores y_m back at z[g + j + m S].  A butterfly reads and writes the
+// same positions, so one buffer suffices, and the spectrum comes out in
+// digit-reversed order (dif_pos).  A radix-16 pass has N/16 <= 64 butterflies:
+// one per lane, its 16 values in registers, one LDS round trip per pass.
+__device__ inline void dft4(double2 &x0, double2 &x1, double2 &x2, double2 &x3) {
+  const double2 s02 = cadd(x0, x2), d02 = csub(x0, x2), s13 = cadd(x1, x3), d13 = csub(x1, x3);
+  const double2 md13 = make_double2(d13.y, -d13.x);  // -i (x1 - x3)
+  x0 = cadd(s02, s13);
+  x1 = cadd(d02, md13);
+  x2 = csub(s02, s13);
+  x3 = csub(d02, md13);
+}
+
+// 16-point DFT as 4 x 4: a[r0 + 4 r1] -> DFTs over r1, twiddles
+// e^{-2 pi i r0 m1 / 16}, DFTs over r0.  Output m = m1 + 4 m0 lands in
+// a[4 m1 + m0].
+__device__ inline void dft16(double2 (&a)[16]) {
+  constexpr double C8 = 0.92387953251128674, S8 = 0.38268343236508977, R2 = 0.70710678118654752;
+#pragma unroll
+  for (int r0 = 0; r0 < 4; ++r0) dft4(a[r0], a[r0 + 4], a[r0 + 8], a[r0 + 12]);
+  a[1 + 4] = cmul(a[1 + 4], make_double2(C8, -S8));    // w^1
+  a[1 + 8] = cmul(a[1 + 8], make_double2(R2, -R2));    // w^2
+  a[1 + 12] = cmul(a[1 + 12], make_double2(S8, -C8));  // w^3
+  a[2 + 4] = cmul(a[2 + 4], make_double2(R2, -R2));    // w^2
+  a[2 + 8] = make_double2(a[2 + 8].y, -a[2 + 8].x);    // w^4 = -i
+  a[2 + 12] = cmul(a[2 + 12], make_double2(-R2, -R2)); // w^6
+  a[3 + 4] = cmul(a[3 + 4], make_double2(S8, -C8));    // w^3
+  a[3 + 8] = cmul(a[3 + 8], make_double2(-R2, -R2));   // w^6
+  a[3 + 12] = cmul(a[3 + 12], make_double2(-C8, S8));  // w^9
+#pragma unroll
+  for (int m1 = 0; m1 < 4; ++m1) dft4(a[4 * m1], a[4 * m1 + 1], a[4 * m1 + 2], a[4 * m1 + 3]);
+}
+
+__device__ inline void fft_wave(double2 *z, int N, const TwSplit &twf, int lane) {
+  int M = N;
+  for (; M >= 16; M >>= 4) {
+    const int S = M >> 4, lS = __builtin_ctz(S);
+    if (lane < (N >> 4)) {
+      const int jj = lane & (S - 1), g = (lane >> lS) * M;
+      double2 a[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) a[r] = z[padc(g + jj + r * S)];
+      const double2 w = twf(jj * (N / M));
+      dft16(a);
+      double2 pw = w;  // w^m by repeated products: within a few ulp of the table's
+#pragma unroll
+      for (int m = 1; m < 16; ++m) {
+        const int idx = 4 * (m & 3) + (m >> 2);
+        a[idx] = cmul(a[idx], pw);
+        if (m < 15) pw = cmul(pw, w);
+      }
+#pragma unroll
+      for (int m = 0; m < 16; ++m) z[padc(g + jj + m * S)] = a[4 * (m & 3) + (m >> 2)];
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the next pass reads other lanes' writes
+  }
+  if (M == 8) {  // radix 2 over blocks of 8 (S = 4), then radix 4 below
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int b = lane + 64 * q;
+      if (b < (N >> 1)) {
+        const int jj = b & 3, g = (b >> 2) * 8;
+        const double2 a0 = z[padc(g + jj)], a1 = z[padc(g + jj + 4)];
+        z[padc(g + jj)] = cadd(a0, a1);
+        z[padc(g + jj + 4)] = cmul(csub(a0, a1), twf(jj * (N / 8)));
+      }
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    M = 4;
+  }
+  if (M == 4) {  // radix 4 over blocks of 4 (S = 1: no twiddles)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int b = lane + 64 * q;
+      if (b < (N >> 2)) {
+        double2 a0 = z[padc(4 * b)], a1 = z[padc(4 * b + 1)], a2 = z[padc(4 * b + 2)], a3 = z[padc(4 * b + 3)];
+        dft4(a0, a1, a2, a3);
+        z[padc(4 * b)] = a0;
+        z[padc(4 * b + 1)] = a1;
+        z[padc(4 * b + 2)] = a2;
+        z[padc(4 * b + 3)] = a3;
+      }
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  } else if (M == 2) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int b = lane + 64 * q;
+      if (b < (N >> 1)) {
+        const double2 a0 = z[padc(2 * b)], a1 = z[padc(2 * b + 1)];
+        z[padc(2 * b)] = cadd(a0, a1);
+        z[padc(2 * b + 1)] = csub(a0, a1);
+      }
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  }
+}
+
+// Position of frequency k in the digit-reversed output of fft_wave: k's
+// digits, least significant first, in the radices of the passes, weight the
+// strides N/16, N/256, ... of those passes.
+__host__ __device__ inline int dif_pos(int k, int N) {
+  int p = 0, M = N;
+  for (; M >= 16; M >>= 4) {
+    p += (k & 15) * (M >> 4);
+    k >>= 4;
+  }
+  if (M == 8) {
+    p += (k & 1) * 4;
+    k >>= 1;
+    M = 4;
+  }
+  if (M == 4) p += k & 3;
+  else if (M == 2) p += k & 1;
+  return p;
+}
+
+// Where coordinate f of the real transform reads the digit-reversed padded
+// spectrum: positions of Z_g and Z_{N-g}, g, and which formula applies
+// (0: f = 0, 1: f = N, 2: f < N, 3: f > N); packed in two ints.
+__device__ inline int2 coord_code(int f, int s) {
+  const int N = s >> 1;
+  const int g = (f == 0 || f == N) ? 0 : (f < N ? f : s - f);
+  const int mode = f == 0 ? 0 : (f == N ? 1 : (f < N ? 2 : 3));
+  const int p1 = g ? padc(dif_pos(g, N)) : 0, p2 = g ? padc(dif_pos(N - g, N)) : 0;
+  return make_int2(p1 | (p2 << 16), g | (mode << 16));
+}
+
+__device__ inline double coord_value(const double2 *Z, int2 cd, const TwSplit &twp, double rs, double r2s) {
+  const int mode = cd.y >> 16, g = cd.y & 0xFFFF;
+  const double2 zg = Z[cd.x & 0xFFFF], zn = Z[cd.x >> 16];
+  if (mode < 2) return (mode == 0 ? zg.x + zg.y : zg.x - zg.y) * rs;
+  const double er = 0.5 * (zg.x + zn.x), ei = 0.5 * (zg.y - zn.y);
+  const double orr = 0.5 * (zg.y + zn.y), oi = -0.5 * (zg.x - zn.x);
+  const double2 w = twp(g);
+  if (mode == 2) return (er + (w.x * orr - w.y * oi)) * r2s;
+  return (ei + (w.x * oi + w.y * orr)) * r2s;
+}
+
+template <typename T> struct WsVec;
+template <> struct WsVec<double> {
+  typedef double V __attribute__((ext_vector_type(2)));
+  typedef uint32_t C __attribute__((ext_vector_type(2)));
+  static constexpr int kW = 2, kU = 8;
+};
+template <> struct WsVec<float> {
+  typedef float V __attribute__((ext_vector_type(4)));
+  typedef uint32_t C __attribute__((ext_vector_type(4)));
+  static constexpr int kW = 4, kU = 4;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kWsThreads, 4) void k_sketch_ws(int64_t m, int64_t n, const T *__restrict__ A, int64_t lda,
+                                                          int s, int log2N, int l, const uint32_t *__restrict__ code,
+                                                          const int32_t *__restrict__ sel,
+                                                          const double2 *__restrict__ twf,
+                                                          const double2 *__restrict__ twp, double *__restrict__ Y,
+                                                          int64_t ldy, uint32_t *__restrict__ next_row) {
+  typedef typename WsVec<T>::V VT;
+  typedef typename WsVec<T>::C CT;
+  constexpr int W = WsVec<T>::kW, U = WsVec<T>::kU;
+  constexpr int64_t kChunk = (int64_t)kWsSem * U * W;  // elements per chunk of a row
+  extern __shared__ double2 lds2[];
+  const int N = s >> 1, NP = padc(N);
+  const int tb = log2N >> 1, nlo = 1 << tb, nhi = N >> tb;
+  double2 *tab = lds2 + 2 * NP;  // split twiddle tables of twf and twp
+  int2 *code_s = reinterpret_cast<int2 *>(tab + 2 * (nlo + nhi));  // per coordinate: coord_code
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int i = tid; i < 2 * NP; i += kWsThreads) lds2[i] = make_double2(0.0, 0.0);
+  for (int i = tid; i < nlo; i += kWsThreads) {
+    tab[i] = twf[i];
+    tab[nlo + nhi + i] = twp[i];
+  }
+  for (int i = tid; i < nhi; i += kWsThreads) {
+    tab[nlo + i] = twf[i << tb];
+    tab[2 * nlo + nhi + i] = twp[i << tb];
+  }
+  for (int q = tid; q < l; q += kWsThreads) code_s[q] = coord_code(sel[q], s);
+  const TwSplit tf{tab, tab + nlo, tb, nlo - 1};
+  const TwSplit tp{tab + nlo + nhi, tab + 2 * nlo + nhi, tb, nlo - 1};
+  // Rows: the block's first K rows strided by the grid (K G <= 3m/4), then
+  // rows from a global counter as blocks go (blocks sharing a CU progress at
+  // different rates; one counter for all rows would serialise on its
+  // address).  Fetched two ahead into a ring of four LDS slots: slot
+  // (it + 2) & 3 is written in iteration it and read from iteration it + 1
+  // on; iteration it reads slots it, it - 1 and it + 1.  A block's rows
+  // increase, so once a slot holds m or more, all later ones do.
+  __shared__ int64_t s_row[4];
+  const int64_t G = gridDim.x, K = (m / G) * 3 / 4;
+  auto fetch = [&](int64_t j) -> int64_t {
+    if (j < K) return (int64_t)blockIdx.x + j * G;
+    const int64_t r = K * G + (int64_t)atomicAdd(next_row, 1u);
+    return r < m ? r : m;
+  };
+  if (tid == 0) {
+    s_row[0] = fetch(0);
+    s_row[1] = s_row[0] < m ? fetch(1) : m;
+  }
+  __syncthreads();
+  const double rs = 1.0 / sqrt((double)s), r2s = sqrt(2.0) * rs;
+
+  // streaming waves: chunks of U vector loads per thread, two register sets
+  // (chunk k + 1 is loaded while chunk k is scattered; the next row's first
+  // chunk before the row barrier)
+  VT va[U], vb[U];
+  CT ca[U], cb[U];
+  const int64_t nch = (n + kChunk - 1) / kChunk;
+  auto load = [&](VT(&v)[U], CT(&c)[U], int64_t row, int64_t k, int tx) __attribute__((always_inline)) {
+    const T *aj = A + row * lda + k * kChunk;
+    const uint32_t *cj = code + k * kChunk;
+    const uint32_t nj = (uint32_t)min<int64_t>(n - k * kChunk, kChunk);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {  // 32-bit offsets from uniform bases; clamped, masked when scattered
+      const uint32_t e = (uint32_t)(u * kWsSem + tx) * W;
+      const uint32_t ee = e < nj ? e : 0;
+      v[u] = *reinterpret_cast<const VT *>(aj + ee);
+      c[u] = *reinterpret_cast<const CT *>(cj + ee);
+    }
+  };
+  auto scatter = [&](const VT(&v)[U], const CT(&c)[U], double *y0, int64_t k, int tx) __attribute__((always_inline)) {
+    const uint32_t nj = (uint32_t)min<int64_t>(n - k * kChunk, kChunk);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t e = (uint32_t)(u * kWsSem + tx) * W;
+      if (e < nj) {
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+          const uint32_t b = code_bucket(c[u][q]);
+          atomicAdd(&y0[b + 2 * (b >> 5)], code_apply(c[u][q], (double)v[u][q]));
+        }
+      }
+    }
+  };
+  // The two roles run separate row loops with the same number of block
+  // barriers (they read the same slots), one per row: the roles' registers are never live
+  // at the same time.  Thread indices are made opaque to loop-invariant code
+  // motion, which would otherwise hoist every lane mask and offset of the
+  // unrolled loops out of the row loop (and spill them).
+  // the transform role rotates with the block index, so that the transform
+  // waves of the blocks sharing a CU sit on different SIMDs
+  const int fw = (int)(blockIdx.x & 3);
+  const int srank = (wave - fw + 3) & 3;  // 0..2 for the streaming waves
+  const int sid = srank * 64 + (tid & 63);
+  if (wave != fw) {
+    if (s_row[0] < m) load(va, ca, s_row[0], 0, sid);
+    for (int it = 0;; ++it) {
+      const int64_t cur = s_row[it & 3], prev = it ? s_row[(it - 1) & 3] : m;
+      if (cur >= m && prev >= m) break;
+      int tx = sid;
+      asm volatile("" : "+v"(tx));
+      if (tx == 0) s_row[(it + 2) & 3] = s_row[(it + 1) & 3] < m ? fetch(it + 2) : m;
+      if (cur < m) {  // stream row cur into buffer it & 1
+        double *y0 = reinterpret_cast<double *>((it & 1) ? lds2 + NP : lds2);
+        for (int64_t k = 0; k < nch; k += 2) {
+          if (k + 1 < nch) load(vb, cb, cur, k + 1, tx);
+          scatter(va, ca, y0, k, tx);
+          if (k + 1 < nch) {
+            if (k + 2 < nch) load(va, ca, cur, k + 2, tx);
+            scatter(vb, cb, y0, k + 1, tx);
+          }
+        }
+        const int64_t nxt = s_row[(it + 1) & 3];
+        if (nxt < m) load(va, ca, nxt, 0, tx);
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int it = 0;; ++it) {
+      const int64_t cur = s_row[it & 3], prev = it ? s_row[(it - 1) & 3] : m;
+      if (cur >= m && prev >= m) break;
+      int tx = tid;
+      asm volatile("" : "+v"(tx));
+      if (prev < m) {  // transform row prev (buffer (it - 1) & 1), write it, clear the buffer
+        double2 *z = ((it - 1) & 1) ? lds2 + NP : lds2;
+        const int ln = tx & 63;
+        fft_wave(z, N, tf, ln);
+        double *yrow = Y + prev * ldy;
+        for (int q0 = 0; q0 < l; q0 += 256) {  // four coordinates per lane: all loads first
+          int2 cd[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) cd[u] = code_s[min(q0 + ln + 64 * u, l - 1)];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int q = q0 + ln + 64 * u;
+            const double v = coord_value(z, cd[u], tp, rs, r2s);
+            if (q < l) yrow[q] = v;
+          }
+        }
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        for (int i = ln; i < NP; i += 64) z[i] = make_double2(0.0, 0.0);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+static size_t sketch_ws_lds_bytes(int s, int l) {
+  const int N = s >> 1, log2N = ilog2_exact(N), b = tw_bits(log2N);
+  return (size_t)(2 * padc(N) + 2 * ((1 << b) + (N >> b))) * sizeof(double2) + (size_t)l * sizeof(int2);
+}
+
 template <typename T>
 static void launch_pf(int pf, dim3 grid, size_t lds, hipStream_t st, int64_t m, int64_t n, const T *A,
                       int64_t lda, int s, int log2N, int l, const uint32_t *code, const int32_t *sel,
@@ -121,7 +446,31 @@ static void launch_pf(int pf, dim3 grid, size_t lds, hipStream_t st, int64_t m, 
 hipError_t launch_sketch_dense(int64_t m, int64_t n, const void *A, int dtype, int64_t lda, int s,
                                int l, const uint32_t *code, const int32_t *sel,
                                const double2 *twf, const double2 *twp, double *Y, int64_t ldy,
-                               int num_cu, hipStream_t st) {
+                               uint32_t *row_counter, int num_cu, hipStream_t st) {
+  const int W = dtype == RLU_F64 ? 2 : 4;
+  if (s >= 8 && s <= 2 * kWsMaxN && n % W == 0 && lda % W == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
+      l <= 1024) {
+    const size_t lds = sketch_ws_lds_bytes(s, l);
+    // blocks per CU as the runtime resolves them (registers, LDS and its
+    // allocation granularity): a grid of resident blocks, each taking every
+    // grid-th row, with no second round of blocks
+    int per_cu = 0;
+    const void *kfn = dtype == RLU_F64 ? (const void *)k_sketch_ws<double> : (const void *)k_sketch_ws<float>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kWsThreads, lds) != hipSuccess || per_cu < 1) {
+      (void)hipGetLastError();
+      per_cu = 1;
+    }
+    per_cu = std::min(per_cu, 4);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)num_cu * per_cu));
+    const int log2N = ilog2_exact(s / 2);
+    if (dtype == RLU_F64)
+      hipLaunchKernelGGL(k_sketch_ws<double>, dim3(grid), dim3(kWsThreads), lds, st, m, n, (const double *)A, lda, s,
+                         log2N, l, code, sel, twf, twp, Y, ldy, row_counter);
+    else
+      hipLaunchKernelGGL(k_sketch_ws<float>, dim3(grid), dim3(kWsThreads), lds, st, m, n, (const float *)A, lda, s,
+                         log2N, l, code, sel, twf, twp, Y, ldy, row_counter);
+    return hipGetLastError();
+  }
   const size_t lds = sketch_lds_bytes(s, l);
   const int per_cu = std::max<int>(1, (int)std::min<size_t>(8, (160 * 1024) / lds));
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)num_cu * per_cu));

@@ -55,6 +55,19 @@ def test_params_bit_exact(n, l, s, seed):
     (64, 300, 2, 2, 9, np.float64),           # s = 2: trivial transform
     (200, 777, 40, 128, 11, np.float32),      # FP32 storage widened exactly
     (200, 8192, 100, 8192, 13, np.float64),   # largest s
+    # wave-specialised path (s <= 2048, n a multiple of the vector width):
+    # every radix sequence of the in-place transform, FP32 storage, chunks of
+    # a row that end ragged, and more rows than resident blocks (rows handed
+    # out through the counter)
+    (3000, 4096, 210, 2048, 21, np.float64),  # 16 16 4
+    (700, 1000, 60, 1024, 22, np.float64),    # 16 16 2
+    (260, 514, 40, 512, 23, np.float64),      # 16 16
+    (90, 3074, 30, 256, 24, np.float64),      # 16 2 4; a chunk of two elements
+    (50, 64, 12, 16, 25, np.float64),         # 8: 2 4
+    (50, 40, 6, 8, 26, np.float64),           # 4
+    (80, 96, 20, 32, 27, np.float64),         # 16
+    (500, 2048, 100, 2048, 28, np.float32),   # FP32 storage, 16-byte loads
+    (9000, 6148, 120, 1024, 29, np.float32),  # FP32, ragged chunk, counter tail
 ])
 def test_sketch_matches_oracle(m, n, l, s, seed, dtype):
     a = np.random.default_rng(seed).standard_normal((m, n)).astype(dtype)
