@@ -18,6 +18,9 @@
 // A^T (A stored K x M); A may be FP32 storage (widened exactly for FP64).
 // Split-K writes per-split partials that a second kernel sums in a fixed
 // order (deterministic).
+#include <type_traits>
+#include <utility>
+
 #include "rlu_device.h"
 #include "rlu_internal.h"
 
@@ -209,6 +212,155 @@ __global__ __launch_bounds__(128 * WGM, 1) void k_gemm(GemmK p) {
       }
 }
 
+// Direct global-to-LDS form for FP64 op(A) = A^T with full 128-row tiles
+// (M a multiple of 128, every K extent a multiple of 16, N even, A and B rows
+// 16-byte aligned).  Each K row of a stage's A tile (128 doubles) and B tile
+// (BN doubles) is copied by global_load_lds_dwordx4 instructions of one wave
+// straight into LDS (16 bytes per lane, lanes contiguous).  Three buffers per
+// operand hold stages s (being multiplied), s + 1 (landed) and s + 2 (in
+// flight), so the loads get two stages to land without holding registers;
+// the waits on them are the explicit ones before each barrier.  B columns at
+// or past N receive copies of the row's first columns: they reach only
+// output columns that are not stored.
+// 16 bytes per lane from global memory straight into LDS (lane i's bytes at
+// lds + 16 i).  A plain device function: the builtin exists only for the
+// device, and the kernel template must also instantiate in the host pass.
+__device__ inline void lds_copy16(const double *g, double *lds) { __builtin_amdgcn_global_load_lds(g, lds, 16, 0, 0); }
+
+template <int FN>
+__global__ __launch_bounds__(512, 1) void k_gemm_dma(GemmK p) {
+  typedef Mfma<double> MF;
+  constexpr int WGM = 4, FM = 2;
+  constexpr int BM = 16 * FM * WGM, BN = 32 * FN;
+  constexpr int H = (BN + 127) / 128;  // copy instructions per B row
+  // a copy instruction writes 128 doubles (64 lanes x 16 bytes) whatever BN
+  // is: B rows are 128 H doubles apart (plus the bank padding), so the lanes
+  // past BN write padding rather than the next row
+  constexpr int AS = pad_stride(BM), BS = pad_stride(128 * H);
+  static_assert(BM == 128 && kBK == 16, "one 1 KB A row per wave instruction, two rows per wave");
+  // separate LDS objects, each named statically below: the compiler then
+  // knows a read of one buffer does not wait for copies into another
+  __shared__ __align__(16) double As0[kBK * AS], As1[kBK * AS], As2[kBK * AS];
+  __shared__ __align__(16) double Bs0[kBK * BS], Bs1[kBK * BS], Bs2[kBK * BS];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave % WGM, wn = wave / WGM;
+  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+  const int64_t kb = (int64_t)blockIdx.z * p.Kc;
+  const int64_t ke = min(p.K, kb + p.Kc);
+  const double *A = reinterpret_cast<const double *>(p.A);
+  const double *B = reinterpret_cast<const double *>(p.B);
+
+  typename MF::acc_t acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = typename MF::acc_t{0, 0, 0, 0};
+
+  auto uniform_ptr = [](const double *q) -> const double * {
+    const uint64_t u = reinterpret_cast<uint64_t>(q);
+    return reinterpret_cast<const double *>(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
+                                            (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u));
+  };
+  // rows 2 wave and 2 wave + 1 of stage k0's tiles into (as, bs)
+  auto copy_stage = [&](double *as, double *bs, int64_t k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int kr = 2 * wave + q;
+      lds_copy16(uniform_ptr(A + (k0 + kr) * p.lda + m0) + 2 * lane, as + kr * AS);
+      const double *brow = uniform_ptr(B + (k0 + kr) * p.ldb + n0);
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        // every lane issues (a fixed count of copies per stage); lanes past
+        // N or the tile re-read the row's start into columns not stored
+        const int c = 128 * h + 2 * lane;
+        const int cc = (c < BN && n0 + c < p.N) ? c : 0;
+        lds_copy16(brow + cc, bs + kr * BS + 128 * h);
+      }
+    }
+  };
+  auto wait_copies = [&](bool newer) {  // all but the newest stage's 2 + 2 H copies landed
+    static_assert(H == 1 || H == 2, "");
+    if (!newer) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    else if (H == 2) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+  };
+  auto compute = [&](const double *asb, const double *bsb) __attribute__((always_inline)) {
+    const double *as = asb + wm * 16 * FM + (lane & 15);
+    const double *bs = bsb + wn * 16 * FN + (lane & 15);
+#pragma unroll
+    for (int kk = 0; kk < kBK / 4; ++kk) {
+      const int kr = kk * 4 + (lane >> 4);
+      double a[FM], b[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) a[i] = as[kr * AS + i * 16];
+#pragma unroll
+      for (int j = 0; j < FN; ++j) b[j] = bs[kr * BS + j * 16];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = MF::step(a[i], b[j], acc[i][j]);
+    }
+  };
+
+  if (kb < ke) {
+    copy_stage(As0, Bs0, kb);
+    const bool m1 = kb + kBK < ke;
+    if (m1) copy_stage(As1, Bs1, kb + kBK);
+    wait_copies(m1);  // stage 0 landed
+    __builtin_amdgcn_s_barrier();
+  }
+  // Stage s is in buffer s mod 3; its copies are issued while stage s - 2 is
+  // multiplied (into the buffer stage s - 3 used).  They are issued every
+  // stage (a fixed count, so the compiler's own waits before the LDS reads
+  // stay exact): without a stage s + 2 the free buffer receives a copy of
+  // stage s, which nothing reads.  After the MFMAs: the wait for stage
+  // s + 1 and a bare barrier (the workgroup fence of __syncthreads would
+  // also wait for the copies still in flight; every wave's LDS reads of
+  // stage s precede its barrier).
+#define RLU_DMA_STEP(ASC, BSC, ASN, BSN, K0)                                         \
+  {                                                                                  \
+    const int64_t k0_ = (K0);                                                        \
+    const bool more1 = k0_ + kBK < ke, more2 = k0_ + 2 * kBK < ke;                   \
+    copy_stage(ASN, BSN, more2 ? k0_ + 2 * kBK : k0_);                               \
+    compute(ASC, BSC);                                                               \
+    if (more1) {                                                                     \
+      wait_copies(true);                                                             \
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");                             \
+      __builtin_amdgcn_s_barrier();                                                  \
+    }                                                                                \
+    __builtin_amdgcn_sched_barrier(0);                                               \
+  }
+  // K extents are multiples of 16 here: whole groups of three stages, then
+  // the zero to two stages left (which start again at buffer 0)
+  const int64_t ns = (ke - kb) / kBK;
+  int64_t k0 = kb;
+  for (int64_t g3 = 0; g3 + 3 <= ns; g3 += 3, k0 += 3 * kBK) {
+    RLU_DMA_STEP(As0, Bs0, As2, Bs2, k0)
+    RLU_DMA_STEP(As1, Bs1, As0, Bs0, k0 + kBK)
+    RLU_DMA_STEP(As2, Bs2, As1, Bs1, k0 + 2 * kBK)
+  }
+  if (k0 < ke) RLU_DMA_STEP(As0, Bs0, As2, Bs2, k0)
+  if (k0 + kBK < ke) RLU_DMA_STEP(As1, Bs1, As0, Bs0, k0 + kBK)
+#undef RLU_DMA_STEP
+
+  // epilogue: plain (beta = 0) or partial stores
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t m = m0 + wm * 16 * FM + i * 16 + MF::row(lane, v);
+        const int64_t n = n0 + wn * 16 * FN + j * 16 + (lane & 15);
+        if (m < p.M && n < p.N) {
+          const double x = acc[i][j][v];
+          if (p.partial) p.C[(int64_t)blockIdx.z * p.cstride + m * p.ldc + n] = x;
+          else p.C[m * p.ldc + n] = p.alpha * x;
+        }
+      }
+}
+
 __global__ void k_splitk_reduce(int64_t M, int64_t N, int splits, const double *__restrict__ parts,
                                 double *__restrict__ C, int64_t ldc, double alpha, double beta) {
   const int64_t total = M * N;
@@ -289,6 +441,21 @@ static hipError_t launch(const GemmArgs &g, int splits, int64_t Kc, double *part
   if (g.trans_a) {
     if (g.gather) return hipErrorInvalidValue;
     if (g.a_dtype == RLU_F32) return dispatch_shape<double, float, true, false>(sh, grid, k, st);
+    const bool full = sh.wgm == 4 && sh.fm == 2 && g.M % 128 == 0 && g.K % kBK == 0 && Kc % kBK == 0 &&
+                      g.N % 2 == 0 && g.lda % 2 == 0 && g.ldb % 2 == 0 &&
+                      ((reinterpret_cast<uintptr_t>(g.A) | reinterpret_cast<uintptr_t>(g.B)) & 15) == 0 &&
+                      (k.partial || g.beta == 0.0);
+    if (full) {
+      switch (sh.fn) {
+#define RLU_FN(F)                                                                     \
+  case F:                                                                             \
+    hipLaunchKernelGGL((k_gemm_dma<F>), grid, dim3(512), 0, st, k); \
+    return hipGetLastError();
+        RLU_FN(4) RLU_FN(6) RLU_FN(7)
+#undef RLU_FN
+        default: break;
+      }
+    }
     return dispatch_shape<double, double, true, false>(sh, grid, k, st);
   }
   if (g.a_dtype != RLU_F64) return hipErrorInvalidValue;

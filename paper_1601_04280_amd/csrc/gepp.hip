@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
   __shared__ int s_wrow[2], s_ok[2];
   __shared__ int s_zero, s_nonfinite;
   __shared__ double pvs[2][2 * NB];  // winner's row, shifted: pvs[p][k] = column j + k (zero padded)
-  __shared__ double cvals[NW][NB];   // each wave's best candidate row (before this step's update), staged
+  __shared__ __align__(16) double cvals[NW][NB];  // each wave's best candidate row (before this step's update), staged
   __shared__ double cmlt[NW];        // and its multiplier of this step
 
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
@@ -210,7 +210,8 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
       for (int g0 = 0; g0 < NB; g0 += kKG)
         if (g0 <= nvals) {
 #pragma unroll
-          for (int k = g0; k < g0 + kKG; ++k) cvals[wave][k] = rv[k];
+          for (int k = g0; k < g0 + kKG; k += 2)  // 16-byte stores (NB and kKG are even)
+            *reinterpret_cast<double2 *>(&cvals[wave][k]) = make_double2(rv[k], rv[k + 1]);
         }
       cmlt[wave] = mo;
     }

@@ -200,7 +200,10 @@ def test_factor_well_conditioned_all_columns():
 
 
 @pytest.mark.parametrize("m,n,k,l,s", [(64, 600, 5, 64, 64), (33, 700, 5, 17, 32), (900, 300, 10, 35, 64),
-                                       (3000, 2000, 100, 150, 1024), (5000, 257, 40, 64, 128)])
+                                       (3000, 2000, 100, 150, 1024), (5000, 257, 40, 64, 128),
+                                       # n a multiple of 128, m of 16, l even: the contraction's
+                                       # direct-to-LDS form (one and two B copies per row)
+                                       (2048, 1024, 50, 100, 256), (3072, 1280, 100, 210, 512)])
 def test_factor_shapes(m, n, k, l, s):
     A = np.random.default_rng(m + n).standard_normal((m, n))
     seed, o = screened_factor(A, k, l, s, 5)
