@@ -27,8 +27,9 @@ __global__ void k_sem_codes(int64_t n, int log2s, uint64_t key_sem, uint64_t key
 // SRFT diagonal d, Fourier twiddles, and the selected coordinates.
 //   twf[k] = exp(-2 pi i k / N), N = s/2 (complex FFT of the packed row)
 //   twp[f] = exp(-2 pi i f / s), f < N   (split of the real-input spectrum)
-// The selection is a partial Fisher-Yates shuffle, sequential by nature; it
-// runs on one thread of block 0 over an identity array of s ints in LDS.
+// The selection is a partial Fisher-Yates shuffle over 0 .. s-1 with
+// counter-based draws; block 0 resolves each selected coordinate
+// independently (see below).
 __global__ void k_srft_params(int s, int l, uint64_t key_signs, uint64_t key_sel,
                               int8_t *__restrict__ d_out, int32_t *__restrict__ sel,
                               double2 *__restrict__ twf, double2 *__restrict__ twp) {
@@ -49,17 +50,28 @@ __global__ void k_srft_params(int s, int l, uint64_t key_signs, uint64_t key_sel
     }
   }
   if (sel == nullptr || blockIdx.x != 0) return;
-  for (int i = threadIdx.x; i < s; i += blockDim.x) idx[i] = i;
+  // Swap i exchanges positions i and j_i (i <= j_i < s); all j_i first.
+  int32_t *jsw = idx;
+  for (int i = threadIdx.x; i < l; i += blockDim.x) {
+    const uint64_t r = draw(key_sel, (uint64_t)i);
+    jsw[i] = i + (int)__umul64hi(r, (uint64_t)(s - i));
+  }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < l; ++i) {
-      const uint64_t r = draw(key_sel, (uint64_t)i);
-      const int j = i + (int)__umul64hi(r, (uint64_t)(s - i));
-      const int t = idx[i];
-      idx[i] = idx[j];
-      idx[j] = t;
-      sel[i] = idx[i];
+  // sel[i] is what position j_i holds just before swap i: its initial value
+  // j_i unless an earlier swap k wrote it (the latest k < i with j_k = j_i),
+  // in which case it is what position k held just before swap k, and so on
+  // back (each step moves to an earlier swap).  Same result as running the
+  // swaps in order, one thread per coordinate.
+  for (int i = threadIdx.x; i < l; i += blockDim.x) {
+    int p = jsw[i], t = i;
+    for (;;) {
+      int k = t - 1;
+      while (k >= 0 && jsw[k] != p) --k;
+      if (k < 0) break;
+      p = k;
+      t = k;
     }
+    sel[i] = p;
   }
 }
 

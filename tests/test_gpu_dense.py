@@ -34,7 +34,8 @@ def rel_fro(a, b):
 # ---------------------------------------------------------------- parameters
 
 @pytest.mark.parametrize("n,l,s,seed", [(512, 30, 256, 1), (1000, 2, 2, 3), (5000, 210, 2048, 2**64 - 5),
-                                        (3, 1, 4, 0), (17000, 520, 4096, 12345)])
+                                        (3, 1, 4, 0), (17000, 520, 4096, 12345),
+                                        (300, 256, 256, 7)])  # l = s: every position selected
 def test_params_bit_exact(n, l, s, seed):
     if l > s:
         pytest.skip("l > s")
