@@ -62,14 +62,17 @@ __global__ void k_srft_params(int s, int l, uint64_t key_signs, uint64_t key_sel
   // in which case it is what position k held just before swap k, and so on
   // back (each step moves to an earlier swap).  Same result as running the
   // swaps in order, one thread per coordinate.
+  // (The search reads every earlier j_k rather than stopping at the first
+  // match from the end: independent LDS reads instead of a dependent chain.)
   for (int i = threadIdx.x; i < l; i += blockDim.x) {
     int p = jsw[i], t = i;
     for (;;) {
-      int k = t - 1;
-      while (k >= 0 && jsw[k] != p) --k;
-      if (k < 0) break;
-      p = k;
-      t = k;
+      int last = -1;
+#pragma unroll 8
+      for (int k = 0; k < t; ++k) last = (jsw[k] == p) ? k : last;
+      if (last < 0) break;
+      p = last;
+      t = last;
     }
     sel[i] = p;
   }
