@@ -119,6 +119,8 @@ rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_pa
   const int l = p->l;
   fp->splits_w = choose_splits(n, l, m, cx.caps.num_cu);
   fp->splits_g = choose_splits(l, l, m, cx.caps.num_cu);
+  fp->splits_i = choose_splits(l, l, l, cx.caps.num_cu);
+  fp->splits_b = choose_splits(n, l, l, cx.caps.num_cu);
   Carver cv;
   plan_sketch_part(cv, *fp, n, l, p->s);
   fp->sketch_total = cv.off;
@@ -127,8 +129,10 @@ rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_pa
   fp->Lhat = cv.take((size_t)m * l * 8);
   fp->Uy = cv.take((size_t)l * l * 8);
   fp->Wt = cv.take((size_t)n * l * 8);
-  fp->parts = cv.take(gemm_f64_splitk_scratch(n, l, fp->splits_w));
-  fp->parts_g = cv.take(gemm_f64_splitk_scratch(l, l, fp->splits_g));  // Gram runs beside the contraction
+  // parts: the contraction's partials, later B^T's; parts_g: the Gram
+  // matrix's (it runs beside the contraction), later G^{-1}'s
+  fp->parts = cv.take(gemm_f64_splitk_scratch(n, l, std::max(fp->splits_w, fp->splits_b)));
+  fp->parts_g = cv.take(gemm_f64_splitk_scratch(l, l, std::max(fp->splits_g, fp->splits_i)));
   fp->Gm = cv.take((size_t)l * l * 8);
   fp->Linv = cv.take((size_t)l * l * 8);
   fp->Dinv = cv.take(chol_scratch_bytes(l));
@@ -314,7 +318,8 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     g.A = at<double>(ws, fp.Linv); g.lda = l; g.a_dtype = RLU_F64; g.trans_a = true;
     g.B = at<double>(ws, fp.Linv); g.ldb = l;
     g.C = at<double>(ws, fp.Ginv); g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
-    if ((e = gemm_f64(g, gs)) != hipSuccess) return hip_fail(e, "inverse Gram");
+    if ((e = gemm_f64_splitk(g, fp.splits_i, at<double>(ws, fp.parts_g), gs)) != hipSuccess)
+      return hip_fail(e, "inverse Gram");
   }
   sm.end(RLU_STAGE_CHOL, gs);
   if (overlap && (e = hipEventRecord(ax.join, ax.aux)) != hipSuccess) return hip_fail(e, "join");
@@ -350,7 +355,8 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     g.A = Wt; g.lda = l; g.a_dtype = RLU_F64; g.trans_a = false;
     g.B = at<double>(ws, fp.Ginv); g.ldb = l;
     g.C = at<double>(ws, fp.Bt); g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
-    if ((e = gemm_f64(g, st)) != hipSuccess) return hip_fail(e, "least-squares product");
+    if ((e = gemm_f64_splitk(g, fp.splits_b, at<double>(ws, fp.parts), st)) != hipSuccess)
+      return hip_fail(e, "least-squares product");
   }
   sm.end(RLU_STAGE_SOLVE, st);
   double *Bt = at<double>(ws, fp.Bt);

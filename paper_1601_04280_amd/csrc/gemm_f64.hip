@@ -375,16 +375,18 @@ __global__ void k_splitk_reduce(int64_t M, int64_t N, int splits, const double *
   }
 }
 
-// Tile shape for an M x N output.  FN (N tile = 32 FN) from 7, 6, 4, 2, 1
-// minimises padded width x (1 + 1/FN): the second factor charges narrow
-// tiles for their extra operand reads per MFMA and extra passes over op(A)
-// (one per N tile).  FM = 2; the 8-wave block (M tile 128) when M is large.
+// Tile shape for an M x N output with inner dimension K.  FN (N tile =
+// 32 FN) from 7, 6, 4, 2, 1 minimises padded width x (1 + 1/FN): the second
+// factor charges narrow tiles for their extra operand reads per MFMA and
+// extra passes over op(A) (one per N tile).  FM = 2; the 8-wave block (M
+// tile 128) when M and K are large (deep products fill the device through
+// K splits), else the 4-wave block (M tile 64, twice the blocks).
 struct Shape {
   int wgm, fm, fn;
   int bm() const { return 16 * fm * wgm; }
   int bn() const { return 32 * fn; }
 };
-static Shape pick_shape(int64_t M, int64_t N) {
+static Shape pick_shape(int64_t M, int64_t N, int64_t K) {
   static const int fns[] = {7, 6, 4, 2, 1};
   int best = 1;
   double best_cost = 1e300;
@@ -392,7 +394,7 @@ static Shape pick_shape(int64_t M, int64_t N) {
     const double cost = (double)(ceil_div(N, 32 * fn) * 32 * fn) * (1.0 + 1.0 / fn);
     if (cost < best_cost) { best_cost = cost; best = fn; }
   }
-  return Shape{M >= 1024 ? 4 : 2, 2, best};
+  return Shape{(M >= 1024 && K >= 1024) ? 4 : 2, 2, best};
 }
 
 template <typename TC, typename TAt, bool TRA, bool GATH, int WGM>
@@ -419,7 +421,7 @@ static hipError_t dispatch_shape(const Shape &sh, dim3 grid, GemmK k, hipStream_
 
 static hipError_t launch(const GemmArgs &g, int splits, int64_t Kc, double *parts, hipStream_t st) {
   if (g.trans_b) return hipErrorInvalidValue;
-  const Shape sh = pick_shape(g.M, g.N);
+  const Shape sh = pick_shape(g.M, g.N, g.K);
   GemmK k;
   k.M = g.M; k.N = g.N; k.K = g.K;
   k.A = g.A; k.lda = g.lda; k.gather = g.gather;
@@ -468,13 +470,15 @@ hipError_t gemm_f64(const GemmArgs &g, hipStream_t st) {
   return launch(g, 1, std::max<int64_t>(g.K, 1), nullptr, st);
 }
 
-// K splits: the count (1 .. 64, each split at least 256 deep) that minimises
-// rounds of co-resident blocks (one per CU) per unit of work; ties go to
-// fewer splits.
+// K splits: the count (1 .. 64, each split at least 256 deep, or 32 deep for
+// products with fewer tiles than CUs) that minimises rounds of co-resident
+// blocks (one per CU) per unit of work; ties go to fewer splits.
 int choose_splits(int64_t M, int64_t N, int64_t K, int num_cu) {
-  const Shape sh = pick_shape(M, N);
+  const Shape sh = pick_shape(M, N, K);
   const int64_t tiles = ceil_div(M, sh.bm()) * ceil_div(N, sh.bn());
-  const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(64, K / 256));
+  // splits at least 256 deep, or 32 deep when the tiles alone leave CUs idle
+  const int64_t depth = tiles < num_cu ? 32 : 256;
+  const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(64, K / depth));
   int64_t best = 1;
   double best_cost = 1e300;
   for (int64_t s = 1; s <= smax; ++s) {

@@ -170,6 +170,7 @@ struct FactorPlan {
   int l, s;
   GeppPlan py, pb;
   int splits_w, splits_g;
+  int splits_i, splits_b;  // G^{-1} = L^{-T} L^{-1} (in parts_g) and B^T = W^T G^{-1} (in parts)
   PrecPlan pp;
   // offsets (bytes) into the workspace
   size_t ctl, code, sel, twf, twp, Y, slots, csc, Lhat, Uy, Wt, parts, parts_g, Gm, Linv, Dinv, Ginv, Bt,
