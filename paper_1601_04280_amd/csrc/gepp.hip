@@ -462,6 +462,86 @@ __global__ __launch_bounds__(256) void k_u12(int l, int j0, int nbp, const doubl
   }
 }
 
+// U12 for 64-column panels by blocked substitution on MFMA: with L11 split
+// into 16 x 16 blocks L_IJ and D_I = L_II^{-1} (each diagonal block inverted
+// once per block by forward substitution, 16 steps), for I = 0 .. 3
+//   X_I <- D_I (X_I - sum_{J < I} L_IJ X_J)
+// on v_mfma_f64_16x16x4.  Each wave owns 16 of the block's 64 columns, so
+// the four phases need no block barrier (a wave reads back only its own
+// columns; its LDS operations complete in order).  Rows past the panel's
+// nbp carry an identity L11 row and zero data.
+typedef double v4d_u __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_u12_mfma(int l, int j0, int nbp, const double *__restrict__ Lhat,
+                                                  const int32_t *__restrict__ rowAt, const double *__restrict__ X,
+                                                  int64_t ldx, double *__restrict__ U) {
+  constexpr int NB = 64, P = NB + 4;  // row stride of the LDS tiles
+  __shared__ double Ls[NB * P];        // L11 (unit lower; identity past nbp)
+  __shared__ double Xs[NB * P];        // the block's 64 columns of X, then of U12
+  __shared__ double Ds[4][16][17];     // inverses of the diagonal blocks
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int j1 = j0 + nbp, cb = j1 + blockIdx.x * NB;
+  block_copy(NB * NB, [&](int e) {
+    const int t = e / NB, u = e % NB;
+    return (t < nbp && u < t) ? Lhat[(int64_t)rowAt[j0 + t] * l + j0 + u] : 0.0;
+  }, [&](int e, double v) {
+    const int t = e / NB, u = e % NB;
+    Ls[t * P + u] = (t == u) ? 1.0 : v;
+  });
+  block_copy(NB * NB, [&](int e) {
+    const int i = e / NB, c = e % NB;
+    return (i < nbp && cb + c < l) ? X[(int64_t)rowAt[j0 + i] * ldx + cb + c] : 0.0;
+  }, [&](int e, double v) { Xs[(e / NB) * P + e % NB] = v; });
+  __syncthreads();
+  if (tid < 64) {  // column c of D_I, I = tid / 16
+    const int I = tid >> 4, c = tid & 15;
+    double x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      double sum = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int u = 0; u < r; ++u) sum = fma(-Ls[(16 * I + r) * P + 16 * I + u], x[u], sum);
+      x[r] = sum;
+      Ds[I][r][c] = sum;
+    }
+  }
+  __syncthreads();
+  const int lr = lane & 15, lk = lane >> 4;
+  const int col = 16 * wave + lr;
+#pragma unroll
+  for (int I = 0; I < 4; ++I) {
+    v4d_u acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = Xs[(16 * I + lk + 4 * v) * P + col];
+#pragma unroll
+    for (int J = 0; J < I; ++J)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const double a = -Ls[(16 * I + lr) * P + 16 * J + 4 * kk + lk];
+        const double b = Xs[(16 * J + 4 * kk + lk) * P + col];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Xs[(16 * I + lk + 4 * v) * P + col] = acc[v];
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the wave's other lanes read these
+    v4d_u r = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const double a = Ds[I][lr][4 * kk + lk];
+      const double b = Xs[(16 * I + 4 * kk + lk) * P + col];
+      r = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, r, 0, 0, 0);
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Xs[(16 * I + lk + 4 * v) * P + col] = r[v];
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  }
+  // U rows j0 .. j1-1, the wave's own columns
+  if (cb + col < l) {
+    for (int i = lk; i < nbp; i += 4) U[(int64_t)(j0 + i) * l + cb + col] = Xs[i * P + col];
+  }
+}
+
 typedef void (*GeppKernel)(GeppKArgs);
 
 static GeppKernel gepp_kernel(int rpt) {
@@ -556,7 +636,7 @@ hipError_t launch_gepp(int64_t rows, int cols, const double *X, int64_t ldx, dou
     const int J2 = cols - j1;
     const dim3 ug((unsigned)ceil_div(J2, 64));
     switch (plan.nb) {
-      case 64: hipLaunchKernelGGL(k_u12<64>, ug, dim3(256), 0, st, cols, j0, nbp, Lhat, rowAt, src, ldsrc, U); break;
+      case 64: hipLaunchKernelGGL(k_u12_mfma, ug, dim3(256), 0, st, cols, j0, nbp, Lhat, rowAt, src, ldsrc, U); break;
       case 32: hipLaunchKernelGGL(k_u12<32>, ug, dim3(256), 0, st, cols, j0, nbp, Lhat, rowAt, src, ldsrc, U); break;
       case 16: hipLaunchKernelGGL(k_u12<16>, ug, dim3(256), 0, st, cols, j0, nbp, Lhat, rowAt, src, ldsrc, U); break;
       case 8: hipLaunchKernelGGL(k_u12<8>, ug, dim3(256), 0, st, cols, j0, nbp, Lhat, rowAt, src, ldsrc, U); break;
