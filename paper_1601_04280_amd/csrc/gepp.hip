@@ -36,7 +36,7 @@ constexpr int kHdrWords = 4;  // |v| lo, |v| hi, position, row
 
 struct GeppKArgs {
   int64_t M;
-  int l, R, SSW;
+  int l, R, SSW, HS;  // SSW: words per candidate row; HS: words per header row (>= blocks)
   int j0, nbp;       // this panel: columns [j0, j0 + nbp)
   const double *X;   // source of the panel columns (row major, ldx)
   int64_t ldx;
@@ -46,60 +46,63 @@ struct GeppKArgs {
   int32_t *ipiv;
   int32_t *posg;     // positions between panel launches (M)
   int32_t *rowAt;    // pivot row of every step (l)
-  uint64_t *slots;   // [2][G][SSW] tagged words, zeroed before the first panel
+  uint64_t *slots;   // [2][G][SSW] tagged words: each block's candidate row
+  uint64_t *hdr;     // [2][kHdrWords][HS] tagged words: the candidates' headers
+                     // (both zeroed before the first panel)
   int32_t *abort_flag;
   uint64_t timeout_ticks;
   rlu_info *info;
   int which;
 };
 
-// ---- arg-max across a wave with DPP --------------------------------------------
-// The candidate order (larger |value|, then smaller position) is total on
-// real candidates, so any reduction order gives the same winner.
+// ---- arg-max across a wave --------------------------------------------------
+// Candidate order: larger |value|, then smaller position.  Positions of real
+// candidates are distinct, so the winner is unique.
 template <int CTRL>
 __device__ inline int dpp_mov(int v) { return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false); }
 
 template <int CTRL>
-__device__ inline Cand cand_dpp(const Cand &c) {
-  const long long bits = __double_as_longlong(c.v);
-  const int lo = dpp_mov<CTRL>((int)bits), hi = dpp_mov<CTRL>((int)(bits >> 32));
-  Cand o;
-  o.v = __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
-  o.pos = dpp_mov<CTRL>(c.pos);
-  o.idx = dpp_mov<CTRL>(c.idx);
-  return o;
+__device__ inline double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_mov<CTRL>((int)b), hi = dpp_mov<CTRL>((int)(b >> 32));
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
 }
-__device__ inline Cand cand_lane(const Cand &c, int src) {
-  const long long bits = __double_as_longlong(c.v);
-  const int lo = __builtin_amdgcn_readlane((int)bits, src), hi = __builtin_amdgcn_readlane((int)(bits >> 32), src);
-  Cand o;
-  o.v = __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
-  o.pos = __builtin_amdgcn_readlane(c.pos, src);
-  o.idx = __builtin_amdgcn_readlane(c.idx, src);
-  return o;
-}
-__device__ inline Cand cand_max(const Cand &a, const Cand &b) {  // field-wise selects keep it in registers
-  const bool t = cand_better(b.v, b.pos, a.v, a.pos);
-  Cand r;
-  r.v = t ? b.v : a.v;
-  r.pos = t ? b.pos : a.pos;
-  r.idx = t ? b.idx : a.idx;
-  return r;
+__device__ inline double readlane_d(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, src), hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
 }
 
-// Winner of the wave's 64 candidates, in every lane: exchanges within quads
-// (quad_perm [1,0,3,2], [2,3,0,1]) and 16-lane rows (row_half_mirror,
-// row_mirror) by DPP, then the four row results by readlane.  Must be called
-// with all lanes active.
-__device__ inline Cand wave_argmax_dpp(Cand c) {
-  c = cand_max(c, cand_dpp<0xB1>(c));
-  c = cand_max(c, cand_dpp<0x4E>(c));
-  c = cand_max(c, cand_dpp<0x141>(c));
-  c = cand_max(c, cand_dpp<0x140>(c));
-  Cand r = cand_lane(c, 0);
-  r = cand_max(r, cand_lane(c, 16));
-  r = cand_max(r, cand_lane(c, 32));
-  r = cand_max(r, cand_lane(c, 48));
+// Winner of the wave's 64 candidates, in every lane.  The largest value by a
+// max reduction (DPP inside 16-lane rows: quad_perm [1,0,3,2], [2,3,0,1],
+// row_half_mirror, row_mirror; readlane across the four rows), its lane by
+// ballot; only when several lanes hold that value does a min reduction of
+// their positions decide.  Values are never NaN (non-finite ones arrive as
+// -1).  Must be called with all lanes active.
+__device__ inline Cand wave_argmax_dpp(const Cand &c) {
+  double m = c.v;
+  m = fmax(m, dpp_f64<0xB1>(m));
+  m = fmax(m, dpp_f64<0x4E>(m));
+  m = fmax(m, dpp_f64<0x141>(m));
+  m = fmax(m, dpp_f64<0x140>(m));
+  m = fmax(fmax(readlane_d(m, 0), readlane_d(m, 16)), fmax(readlane_d(m, 32), readlane_d(m, 48)));
+  const bool top = (c.v == m);
+  uint64_t bal = __ballot(top);
+  if (__popcll(bal) > 1) {
+    int p = top ? c.pos : 0x7fffffff;
+    p = min(p, dpp_mov<0xB1>(p));
+    p = min(p, dpp_mov<0x4E>(p));
+    p = min(p, dpp_mov<0x141>(p));
+    p = min(p, dpp_mov<0x140>(p));
+    p = min(min(__builtin_amdgcn_readlane(p, 0), __builtin_amdgcn_readlane(p, 16)),
+            min(__builtin_amdgcn_readlane(p, 32), __builtin_amdgcn_readlane(p, 48)));
+    bal = __ballot(top && c.pos == p);
+  }
+  const int L = __builtin_ctzll(bal);  // m is some lane's value: bal != 0
+  Cand r;
+  r.v = m;
+  r.pos = __builtin_amdgcn_readlane(c.pos, L);
+  r.idx = __builtin_amdgcn_readlane(c.idx, L);
   return r;
 }
 
@@ -109,12 +112,14 @@ __device__ inline double pivot_mag(double v) {
 }
 
 // Header of a published candidate: |value| (two words), position, row.
-__device__ inline void put_header(uint64_t *sl, const Cand &c, int row, uint32_t tag) {
+// Word w of every block's header sits in row w of a [4][hs] array, so the
+// poll's loads (one block per lane) read consecutive words.
+__device__ inline void put_header(uint64_t *hp, int64_t hs, const Cand &c, int row, uint32_t tag) {
   const uint64_t b = (uint64_t)__double_as_longlong(c.v);
-  tw_put(sl + 0, (uint32_t)b, tag);
-  tw_put(sl + 1, (uint32_t)(b >> 32), tag);
-  tw_put(sl + 2, (uint32_t)c.pos, tag);
-  tw_put(sl + 3, (uint32_t)row, tag);
+  tw_put(hp, (uint32_t)b, tag);
+  tw_put(hp + hs, (uint32_t)(b >> 32), tag);
+  tw_put(hp + 2 * hs, (uint32_t)c.pos, tag);
+  tw_put(hp + 3 * hs, (uint32_t)row, tag);
 }
 
 // Block-wide copy of `total` values into LDS: load(e) -> dst(e), with eight
@@ -143,14 +148,15 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
   constexpr int NW = kGeppThreads / 64;
   constexpr int kKG = NB < 8 ? NB : 8;  // column group of the uniform skips
   // per-step state, double-buffered by step parity so that two block
-  // barriers per step suffice (see the step loop)
+  // barriers per step suffice (see the step loop); cvals and cmlt are written
+  // and read by one wave between the barriers of a step
   __shared__ Cand s_red[2][NW];
   __shared__ Cand s_win[2];
   __shared__ int s_wrow[2], s_ok[2];
   __shared__ int s_zero, s_nonfinite;
   __shared__ double pvs[2][2 * NB];  // winner's row, shifted: pvs[p][k] = column j + k (zero padded)
-  __shared__ __align__(16) double cvals[NW][NB];  // each wave's best candidate row (before this step's update), staged
-  __shared__ double cmlt[NW];        // and its multiplier of this step
+  __shared__ __align__(16) double cvals[NB];  // the block winner's row (before this step's update), staged
+  __shared__ double cmlt;                     // and its multiplier of this step
 
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -180,70 +186,66 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
     for (int k = 0; k < NB; ++k) x[q][k] = (live && k < nbp) ? a.X[row[q] * a.ldx + j0 + k] : 0.0;
   }
 
-  // Block arg-max of the threads' candidates with one barrier: each wave's
-  // winning lane stages its row in that wave's LDS slot before the barrier;
-  // after it, wave 0 publishes the block's winner (tagged values, then the
-  // header) and only then goes on to poll, so a block's own publication is
-  // never held up behind its polling.
+  // Block arg-max of the threads' candidates with one barrier (fence-free:
+  // only LDS is exchanged): each wave's winner goes to s_red; after the
+  // barrier every wave picks the block's winner from the NW entries, wave 0
+  // publishes its header at once, and only the winning wave stages the
+  // winner's row in LDS (its owning lane writes it; LDS operations of one wave
+  // complete in order) and publishes the values, tagged, one per lane.
+  // Other blocks read the values only after they have seen every header, so
+  // the staging stays off the exchange's critical path.
   // The staged row is the candidate's row before this step's update, with
-  // its multiplier; with pv != nullptr wave 0's lanes apply the update
-  // (x[k + 1] - mlt pv[k + 1]) while publishing, which the block's other rows
-  // get only afterwards.
-  auto propose = [&](const Cand &cand, int owner_q, int par, uint64_t *sl, int nvals, uint32_t tag,
+  // its multiplier; with pv != nullptr the publishing lanes apply the update
+  // (x[k + 1] - mlt pv[k + 1]), which the block's other rows get afterwards.
+  auto propose = [&](const Cand &cand, int owner_q, int par, uint64_t *sl, uint64_t *hp, int nvals, uint32_t tag,
                      const double *pv, const double *mltq) __attribute__((always_inline)) {
     const Cand wb = wave_argmax_dpp(cand);
-    if (wb.idx >= 0 && tid == wb.idx % kGeppThreads) {  // this lane won its wave: stage row owner_q
-      double rv[NB];
-      double mo = mltq ? mltq[0] : 0.0;
-#pragma unroll
-      for (int k = 0; k < NB; ++k) rv[k] = x[0][k];
-#pragma unroll
-      for (int q = 1; q < RPT; ++q) {
-        const bool take = (q == owner_q);
-        if (mltq) mo = take ? mltq[q] : mo;
-#pragma unroll
-        for (int k = 0; k < NB; ++k) rv[k] = take ? x[q][k] : rv[k];
-      }
-      // only the values the publication reads (indices up to nvals), in
-      // groups of kKG under a uniform branch
-#pragma unroll
-      for (int g0 = 0; g0 < NB; g0 += kKG)
-        if (g0 <= nvals) {
-#pragma unroll
-          for (int k = g0; k < g0 + kKG; k += 2)  // 16-byte stores (NB and kKG are even)
-            *reinterpret_cast<double2 *>(&cvals[wave][k]) = make_double2(rv[k], rv[k + 1]);
-        }
-      cmlt[wave] = mo;
-    }
     if (lane == 0) s_red[par][wave] = wb;
-    __syncthreads();
-    if (wave == 0) {
-      // one round of LDS reads: every wave's winner, staged value and
-      // multiplier for this lane's column (nvals <= NB <= 64: one per lane);
-      // the block's winner then selects among them in registers
-      const int ci = min(lane + (pv ? 1 : 0), NB - 1);
-      Cand r[NW];
-      double cvw[NW], mow[NW];
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    Cand best = s_red[par][0];
+    int bw = 0;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        r[w] = s_red[par][w];
-        cvw[w] = cvals[w][ci];
-        mow[w] = cmlt[w];
-      }
-      const double pvc = pv ? pv[ci] : 0.0;
-      Cand best = r[0];
-      double cv = cvw[0], mo = mow[0];
+    for (int w = 1; w < NW; ++w) {
+      const Cand r = s_red[par][w];
+      const bool t = cand_better(r.v, r.pos, best.v, best.pos);
+      best.v = t ? r.v : best.v;
+      best.pos = t ? r.pos : best.pos;
+      best.idx = t ? r.idx : best.idx;
+      bw = t ? w : bw;
+    }
+    if (wave == 0 && lane == 0) put_header(hp, a.HS, best, best.idx >= 0 ? (int)(r0 + best.idx) : -1, tag);
+    if (wave == bw && best.idx >= 0) {
+      if (tid == best.idx % kGeppThreads) {  // the winning lane stages row owner_q
+        double rv[NB];
+        double mo = mltq ? mltq[0] : 0.0;
 #pragma unroll
-      for (int w = 1; w < NW; ++w) {
-        const bool t = cand_better(r[w].v, r[w].pos, best.v, best.pos);
-        best.v = t ? r[w].v : best.v;
-        best.pos = t ? r[w].pos : best.pos;
-        best.idx = t ? r[w].idx : best.idx;
-        cv = t ? cvw[w] : cv;
-        mo = t ? mow[w] : mo;
+        for (int k = 0; k < NB; ++k) rv[k] = x[0][k];
+#pragma unroll
+        for (int q = 1; q < RPT; ++q) {
+          const bool take = (q == owner_q);
+          if (mltq) mo = take ? mltq[q] : mo;
+#pragma unroll
+          for (int k = 0; k < NB; ++k) rv[k] = take ? x[q][k] : rv[k];
+        }
+        // only the values the publication reads (indices up to nvals), in
+        // groups of kKG under a uniform branch
+#pragma unroll
+        for (int g0 = 0; g0 < NB; g0 += kKG)
+          if (g0 <= nvals) {
+#pragma unroll
+            for (int k = g0; k < g0 + kKG; k += 2)  // 16-byte stores (NB and kKG are even)
+              *reinterpret_cast<double2 *>(&cvals[k]) = make_double2(rv[k], rv[k + 1]);
+          }
+        cmlt = mo;
       }
-      if (best.idx >= 0 && lane < nvals) tw_put_f64(sl + kHdrWords + 2 * lane, pv ? cv - mo * pvc : cv, tag);
-      if (lane == 0) put_header(sl, best, best.idx >= 0 ? (int)(r0 + best.idx) : -1, tag);
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      if (lane < nvals) {  // nvals <= NB <= 64: one value per lane
+        const int ci = min(lane + (pv ? 1 : 0), NB - 1);
+        const double cv = cvals[ci];
+        tw_put_f64(sl + 2 * lane, pv ? cv - cmlt * pv[ci] : cv, tag);
+      }
     }
   };
 
@@ -257,20 +259,22 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
         if (cand_better(av, pos[q], cand.v, cand.pos)) { cand = Cand{av, pos[q], tid + kGeppThreads * q}; owner_q = q; }
       }
     }
-    propose(cand, owner_q, 1, a.slots + ((size_t)(j0 & 1) * G + g) * a.SSW, nbp, (uint32_t)(j0 + 1), nullptr,
-            nullptr);
+    propose(cand, owner_q, 1, a.slots + ((size_t)(j0 & 1) * G + g) * a.SSW,
+            a.hdr + (size_t)(j0 & 1) * kHdrWords * a.HS + g, nbp, (uint32_t)(j0 + 1), nullptr, nullptr);
   }
 
   // Step c uses buffers [c & 1]: wave 0 fills them before barrier S1(c); the
   // other waves read them after S1(c); the next writes to the same buffers
   // come at step c + 2, after every wave has passed S1(c + 1), hence done
-  // with step c.  S2(c) is the barrier inside propose; cvals is rewritten at
-  // step c + 1 only after S1(c + 1), which wave 0 reaches after publishing.
+  // with step c.  S2(c) is the barrier inside propose (s_red[c & 1] too);
+  // cvals is rewritten at step c + 1 only after S2(c + 1), which every wave
+  // reaches after its part of step c's publication.
   for (int c = 0; c < nbp; ++c) {
     const int j = j0 + c, par = c & 1;
     const int rem = nbp - c;  // columns j .. j1-1 still in the panel
     const uint32_t tag = (uint32_t)(j + 1);
     const uint64_t *slp = a.slots + (size_t)(j & 1) * G * a.SSW;
+    const uint64_t *hpp = a.hdr + (size_t)(j & 1) * kHdrWords * a.HS;
     if (wave == 0) {  // all headers of step j -> winner (G <= 256: <= 4 slots per lane)
       const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
       uint64_t h0[4], h1[4], h2[4], h3[4] = {0, 0, 0, 0};
@@ -281,11 +285,11 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
         for (int qq = 0; qq < 4; ++qq) {
           const int sidx = lane + 64 * qq;
           if (sidx < G) {
-            const uint64_t *sl = slp + (size_t)sidx * a.SSW;
-            h0[qq] = tw_get(sl);
-            h1[qq] = tw_get(sl + 1);
-            h2[qq] = tw_get(sl + 2);
-            h3[qq] = tw_get(sl + 3);
+            const uint64_t *hq = hpp + sidx;
+            h0[qq] = tw_get(hq);
+            h1[qq] = tw_get(hq + a.HS);
+            h2[qq] = tw_get(hq + 2 * a.HS);
+            h3[qq] = tw_get(hq + 3 * a.HS);
             ready &= (tw_tag(h0[qq]) == tag) & (tw_tag(h1[qq]) == tag) & (tw_tag(h2[qq]) == tag) &
                      (tw_tag(h3[qq]) == tag);
           }
@@ -319,8 +323,8 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
         if (lane < rem) {
           uint64_t lo, hi;
           for (uint32_t it = 1;; ++it) {
-            lo = tw_get(wsl + kHdrWords + 2 * lane);
-            hi = tw_get(wsl + kHdrWords + 2 * lane + 1);
+            lo = tw_get(wsl + 2 * lane);
+            hi = tw_get(wsl + 2 * lane + 1);
             if (tw_tag(lo) == tag && tw_tag(hi) == tag) break;
             if ((it & 255) == 0 && !poll_ok(t0, tmo, a.abort_flag)) { ok = 0; break; }
           }
@@ -366,7 +370,8 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
       }
     }
     if (next)
-      propose(cand, owner_q, par, a.slots + ((size_t)((j + 1) & 1) * G + g) * a.SSW, rem - 1, tag + 1, pv, mltq);
+      propose(cand, owner_q, par, a.slots + ((size_t)((j + 1) & 1) * G + g) * a.SSW,
+              a.hdr + (size_t)((j + 1) & 1) * kHdrWords * a.HS + g, rem - 1, tag + 1, pv, mltq);
     if (nonfinite) atomicAdd(&s_nonfinite, nonfinite);
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
@@ -570,16 +575,24 @@ bool plan_gepp(int64_t rows, int cols, const DevCaps &caps, GeppPlan *plan, std:
   plan->R = (int)R;
   plan->nb = nb;
   plan->multi = cols > nb;
-  plan->slot_stride = (int)align_up(kHdrWords + 2 * nb, 16);  // words
+  plan->slot_stride = (int)align_up(2 * nb, 16);  // words
   plan->lds = 0;
   return true;
 }
 
-// slots (2 x G x slot_stride words), positions (rows ints), pivot rows (cols
-// ints), and the row-major working copy of the trailing columns when the
-// factorization has more than one panel
+// header rows: a multiple of 64 words, at least one per block
+static int64_t header_stride(const GeppPlan &plan) { return align_up((int64_t)plan.G, 64); }
+
+// exchange words (candidate rows 2 x G x slot_stride, headers 2 x 4 x
+// header_stride), positions (rows ints), pivot rows (cols ints), and the
+// row-major working copy of the trailing columns when the factorization has
+// more than one panel
+static size_t exchange_bytes(const GeppPlan &plan) {
+  return align_up(((size_t)2 * plan.G * plan.slot_stride + (size_t)2 * kHdrWords * header_stride(plan)) * 8, 256);
+}
+
 size_t gepp_workspace_bytes(int64_t rows, int cols, const GeppPlan &plan) {
-  size_t b = align_up((size_t)2 * plan.G * plan.slot_stride * 8, 256);
+  size_t b = exchange_bytes(plan);
   b += align_up((size_t)rows * 4, 256) + align_up((size_t)cols * 4, 256);
   if (plan.multi) b += align_up((size_t)rows * cols * 8, 256);
   return b;
@@ -591,8 +604,9 @@ hipError_t launch_gepp(int64_t rows, int cols, const double *X, int64_t ldx, dou
   GeppKernel k = gepp_kernel(64 / plan.nb);
   if (!k) return hipErrorInvalidValue;
   char *w = reinterpret_cast<char *>(ws);
-  const size_t slot_bytes = align_up((size_t)2 * plan.G * plan.slot_stride * 8, 256);
+  const size_t slot_bytes = exchange_bytes(plan);
   uint64_t *slots = reinterpret_cast<uint64_t *>(w);
+  uint64_t *hdr = slots + (size_t)2 * plan.G * plan.slot_stride;
   int32_t *posg = reinterpret_cast<int32_t *>(w + slot_bytes);
   int32_t *rowAt = reinterpret_cast<int32_t *>(w + slot_bytes + align_up((size_t)rows * 4, 256));
   double *Wk = reinterpret_cast<double *>(w + slot_bytes + align_up((size_t)rows * 4, 256) +
@@ -612,6 +626,7 @@ hipError_t launch_gepp(int64_t rows, int cols, const double *X, int64_t ldx, dou
   a.l = cols;
   a.R = plan.R;
   a.SSW = plan.slot_stride;
+  a.HS = (int)header_stride(plan);
   a.ldx = ldsrc;
   a.X = src;
   a.Lhat = Lhat;
@@ -621,6 +636,7 @@ hipError_t launch_gepp(int64_t rows, int cols, const double *X, int64_t ldx, dou
   a.posg = posg;
   a.rowAt = rowAt;
   a.slots = slots;
+  a.hdr = hdr;
   a.abort_flag = abort_flag;
   a.timeout_ticks = 200000000ull;  // 2 s of the 100 MHz counter
   a.info = info;
