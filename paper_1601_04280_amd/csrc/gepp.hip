@@ -113,13 +113,12 @@ __device__ inline double pivot_mag(double v) {
 
 // Header of a published candidate: |value| (two words), position, row.
 // Word w of every block's header sits in row w of a [4][hs] array, so the
-// poll's loads (one block per lane) read consecutive words.
-__device__ inline void put_header(uint64_t *hp, int64_t hs, const Cand &c, int row, uint32_t tag) {
+// poll's loads (one block per lane) read consecutive words.  Lane w writes
+// word w: one store instruction for the header.
+__device__ inline void put_header_word(uint64_t *hp, int64_t hs, const Cand &c, int row, uint32_t tag, int w) {
   const uint64_t b = (uint64_t)__double_as_longlong(c.v);
-  tw_put(hp, (uint32_t)b, tag);
-  tw_put(hp + hs, (uint32_t)(b >> 32), tag);
-  tw_put(hp + 2 * hs, (uint32_t)c.pos, tag);
-  tw_put(hp + 3 * hs, (uint32_t)row, tag);
+  const uint32_t d = w == 0 ? (uint32_t)b : w == 1 ? (uint32_t)(b >> 32) : w == 2 ? (uint32_t)c.pos : (uint32_t)row;
+  tw_put(hp + w * hs, d, tag);
 }
 
 // Block-wide copy of `total` values into LDS: load(e) -> dst(e), with eight
@@ -215,7 +214,7 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
       best.idx = t ? r.idx : best.idx;
       bw = t ? w : bw;
     }
-    if (wave == 0 && lane == 0) put_header(hp, a.HS, best, best.idx >= 0 ? (int)(r0 + best.idx) : -1, tag);
+    if (wave == 0 && lane < kHdrWords) put_header_word(hp, a.HS, best, best.idx >= 0 ? (int)(r0 + best.idx) : -1, tag, lane);
     if (wave == bw && best.idx >= 0) {
       if (tid == best.idx % kGeppThreads) {  // the winning lane stages row owner_q
         double rv[NB];
@@ -337,7 +336,10 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
       }
       if (lane == 0) { s_win[par] = best; s_ok[par] = ok; }
     }
-    __syncthreads();  // S1(c)
+    // S1(c), fence-free: wave 0 hands over LDS values only
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
     if (!s_ok[par]) return;
     const Cand win = s_win[par];
     const int wrow = s_wrow[par], wpos = win.pos;
@@ -361,7 +363,6 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
       mltq[q] = (live[q] && !zero) ? x[q][0] / piv : 0.0;
       x1[q] = x[q][1] - mltq[q] * pv[1];
       if (live[q]) {
-        a.Lhat[row[q] * l + j] = mltq[q];
         if (next) {
           const double av = pivot_mag(x1[q]);
           nonfinite += (av < 0.0);
@@ -376,6 +377,7 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       if (live[q]) {
+        a.Lhat[row[q] * l + j] = mltq[q];
         x[q][0] = x1[q];
         // columns from rem on are zero and stay zero (pv is zero padded):
         // whole groups of kKG columns past rem are skipped (uniform branch)
