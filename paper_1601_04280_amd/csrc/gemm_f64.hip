@@ -285,22 +285,27 @@ __global__ __launch_bounds__(512, 1) void k_gemm_dma(GemmK p) {
     else if (H == 2) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
     else asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
   };
-  auto compute = [&](const double *asb, const double *bsb) __attribute__((always_inline)) {
+  // a stage's operand fragments, all four k steps, into registers
+  double fa[kBK / 4][FM], fb[kBK / 4][FN];
+  auto load_frags = [&](const double *asb, const double *bsb) __attribute__((always_inline)) {
     const double *as = asb + wm * 16 * FM + (lane & 15);
     const double *bs = bsb + wn * 16 * FN + (lane & 15);
 #pragma unroll
     for (int kk = 0; kk < kBK / 4; ++kk) {
       const int kr = kk * 4 + (lane >> 4);
-      double a[FM], b[FN];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) a[i] = as[kr * AS + i * 16];
+      for (int i = 0; i < FM; ++i) fa[kk][i] = as[kr * AS + i * 16];
 #pragma unroll
-      for (int j = 0; j < FN; ++j) b[j] = bs[kr * BS + j * 16];
+      for (int j = 0; j < FN; ++j) fb[kk][j] = bs[kr * BS + j * 16];
+    }
+  };
+  auto mfmas = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int kk = 0; kk < kBK / 4; ++kk)
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = MF::step(a[i], b[j], acc[i][j]);
-    }
+        for (int j = 0; j < FN; ++j) acc[i][j] = MF::step(fa[kk][i], fb[kk][j], acc[i][j]);
   };
 
   if (kb < ke) {
@@ -311,7 +316,10 @@ __global__ __launch_bounds__(512, 1) void k_gemm_dma(GemmK p) {
     __builtin_amdgcn_s_barrier();
   }
   // Stage s is in buffer s mod 3; its copies are issued while stage s - 2 is
-  // multiplied (into the buffer stage s - 3 used).  They are issued every
+  // multiplied (into the buffer stage s - 3 used), right after that stage's
+  // fragments have been read into registers: a wait the compiler puts before
+  // those LDS reads then covers only copies issued a stage earlier, never the
+  // ones just issued.  They are issued every
   // stage (a fixed count, so the compiler's own waits before the LDS reads
   // stay exact): without a stage s + 2 the free buffer receives a copy of
   // stage s, which nothing reads.  After the MFMAs: the wait for stage
@@ -322,8 +330,9 @@ __global__ __launch_bounds__(512, 1) void k_gemm_dma(GemmK p) {
   {                                                                                  \
     const int64_t k0_ = (K0);                                                        \
     const bool more1 = k0_ + kBK < ke, more2 = k0_ + 2 * kBK < ke;                   \
+    load_frags(ASC, BSC);                                                            \
     copy_stage(ASN, BSN, more2 ? k0_ + 2 * kBK : k0_);                               \
-    compute(ASC, BSC);                                                               \
+    mfmas();                                                                         \
     if (more1) {                                                                     \
       wait_copies(true);                                                             \
       asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");                             \
