@@ -285,27 +285,23 @@ __global__ __launch_bounds__(512, 1) void k_gemm_dma(GemmK p) {
     else if (H == 2) asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
     else asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
   };
-  // a stage's operand fragments, all four k steps, into registers
+  // operand fragments of the four k steps of a stage, in registers; k step
+  // kk + 1 is read while k step kk is multiplied
   double fa[kBK / 4][FM], fb[kBK / 4][FN];
-  auto load_frags = [&](const double *asb, const double *bsb) __attribute__((always_inline)) {
+  auto load_kk = [&](const double *asb, const double *bsb, int kk) __attribute__((always_inline)) {
     const double *as = asb + wm * 16 * FM + (lane & 15);
     const double *bs = bsb + wn * 16 * FN + (lane & 15);
+    const int kr = kk * 4 + (lane >> 4);
 #pragma unroll
-    for (int kk = 0; kk < kBK / 4; ++kk) {
-      const int kr = kk * 4 + (lane >> 4);
+    for (int i = 0; i < FM; ++i) fa[kk][i] = as[kr * AS + i * 16];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) fa[kk][i] = as[kr * AS + i * 16];
-#pragma unroll
-      for (int j = 0; j < FN; ++j) fb[kk][j] = bs[kr * BS + j * 16];
-    }
+    for (int j = 0; j < FN; ++j) fb[kk][j] = bs[kr * BS + j * 16];
   };
-  auto mfmas = [&]() __attribute__((always_inline)) {
+  auto mfma_kk = [&](int kk) __attribute__((always_inline)) {
 #pragma unroll
-    for (int kk = 0; kk < kBK / 4; ++kk)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j) acc[i][j] = MF::step(fa[kk][i], fb[kk][j], acc[i][j]);
+      for (int j = 0; j < FN; ++j) acc[i][j] = MF::step(fa[kk][i], fb[kk][j], acc[i][j]);
   };
 
   if (kb < ke) {
@@ -316,10 +312,10 @@ __global__ __launch_bounds__(512, 1) void k_gemm_dma(GemmK p) {
     __builtin_amdgcn_s_barrier();
   }
   // Stage s is in buffer s mod 3; its copies are issued while stage s - 2 is
-  // multiplied (into the buffer stage s - 3 used), right after that stage's
-  // fragments have been read into registers: a wait the compiler puts before
-  // those LDS reads then covers only copies issued a stage earlier, never the
-  // ones just issued.  They are issued every
+  // multiplied (into the buffer stage s - 3 used), right after the first k
+  // step's fragments of stage s - 2 have been read: a wait the compiler puts
+  // before those LDS reads then covers only copies issued a stage earlier,
+  // never the ones just issued (the later reads get no wait).  They are issued every
   // stage (a fixed count, so the compiler's own waits before the LDS reads
   // stay exact): without a stage s + 2 the free buffer receives a copy of
   // stage s, which nothing reads.  After the MFMAs: the wait for stage
@@ -330,9 +326,15 @@ __global__ __launch_bounds__(512, 1) void k_gemm_dma(GemmK p) {
   {                                                                                  \
     const int64_t k0_ = (K0);                                                        \
     const bool more1 = k0_ + kBK < ke, more2 = k0_ + 2 * kBK < ke;                   \
-    load_frags(ASC, BSC);                                                            \
+    load_kk(ASC, BSC, 0);                                                            \
     copy_stage(ASN, BSN, more2 ? k0_ + 2 * kBK : k0_);                               \
-    mfmas();                                                                         \
+    load_kk(ASC, BSC, 1);                                                            \
+    mfma_kk(0);                                                                      \
+    load_kk(ASC, BSC, 2);                                                            \
+    mfma_kk(1);                                                                      \
+    load_kk(ASC, BSC, 3);                                                            \
+    mfma_kk(2);                                                                      \
+    mfma_kk(3);                                                                      \
     if (more1) {                                                                     \
       wait_copies(true);                                                             \
       asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");                             \
