@@ -202,9 +202,11 @@ struct StageMarks {
 static rlu_status begin_timing(rlu_ctx_impl &cx, StageMarks &sm) {
   StageTimer &t = cx.timer;
   while (t.pool.size() < t.used + 2 * RLU_NUM_STAGES) {
+    // timing only (read after the caller synchronises): no system-scope
+    // fence, i.e. no cache write-back and invalidation at each stage boundary
     hipEvent_t e;
-    hipError_t err = hipEventCreate(&e);
-    if (err != hipSuccess) return hip_fail(err, "hipEventCreate");
+    hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
+    if (err != hipSuccess) return hip_fail(err, "hipEventCreateWithFlags");
     t.pool.push_back(e);
   }
   for (int i = 0; i < 2 * RLU_NUM_STAGES; ++i) sm.ev[i] = t.pool[t.used + i];

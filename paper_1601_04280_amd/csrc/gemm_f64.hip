@@ -389,7 +389,7 @@ __global__ void k_splitk_reduce(int64_t M, int64_t N, int splits, const double *
 // Tile shape for an M x N output with inner dimension K.  FN (N tile =
 // 32 FN) from 7, 6, 4, 2, 1 minimises padded width x (1 + 1/FN): the second
 // factor charges narrow tiles for their extra operand reads per MFMA and
-// extra passes over op(A) (one per N tile).  FM = 2; the 8-wave block (M
+// extra passes over op(A) (one per N tile); at most 2 for K <= 128.  FM = 2; the 8-wave block (M
 // tile 128) when M and K are large (deep products fill the device through
 // K splits), else the 4-wave block (M tile 64, twice the blocks).
 struct Shape {
@@ -405,6 +405,9 @@ static Shape pick_shape(int64_t M, int64_t N, int64_t K) {
     const double cost = (double)(ceil_div(N, 32 * fn) * 32 * fn) * (1.0 + 1.0 / fn);
     if (cost < best_cost) { best_cost = cost; best = fn; }
   }
+  // shallow products (the LU's trailing updates) are bound by load latency
+  // rather than by operand traffic: narrow tiles, several blocks per CU
+  if (K <= 128 && best > 2) best = 2;
   return Shape{(M >= 1024 && K >= 1024) ? 4 : 2, 2, best};
 }
 
