@@ -89,20 +89,22 @@ def input_bytes(A):
 
 
 def run(rlu, A, w, precision, steps, warmup, ctx):
-    """Warm-up, then `steps` timed decompositions; returns timings and the output."""
+    """Warm-up, then `steps` timed decompositions; returns timings and the output.
+    The bench owns the device, so the calls say so (RLU_FLAG_EXCLUSIVE: the LU
+    panels are ordinary launches instead of cooperative ones)."""
     import torch
     kw = dict(k=w["k"], l=w["l"], s=w["s"], seed=SEED, ctx=ctx, precision=precision)
     if isinstance(A, tuple):
         kw["csr"] = A
         A = None
-    out = rlu.factor(A, **kw)                                   # allocates outputs, checks status
+    out = rlu.factor(A, flags=rlu.RLU_FLAG_EXCLUSIVE, **kw)     # allocates outputs, checks status
     for _ in range(warmup):
-        rlu.factor(A, out=out, check=False, **kw)
+        rlu.factor(A, out=out, check=False, flags=rlu.RLU_FLAG_EXCLUSIVE, **kw)
     torch.cuda.synchronize()
     ctx.stage_times()                                           # clear
     t0 = time.perf_counter()
     for _ in range(steps):
-        rlu.factor(A, out=out, check=False, flags=rlu.RLU_FLAG_TIMING, **kw)
+        rlu.factor(A, out=out, check=False, flags=rlu.RLU_FLAG_TIMING | rlu.RLU_FLAG_EXCLUSIVE, **kw)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stages, calls = ctx.stage_times()
@@ -351,7 +353,7 @@ def main():
         "dtype": precision,
         "data": "synthetic" if not args.gaussian_data else "synthetic-gaussian",
         "config": {"workload": args.workload, "m": w["m"], "n": w["n"], "k": w["k"], "l": w["l"], "s": w["s"],
-                   "storage": storage, "precision": precision},
+                   "storage": storage, "precision": precision, "launch": "exclusive device"},
         "roofline": roof,
         "sketch": sk,
         "stages_ms": {k: round(v, 4) for k, v in per.items()},

@@ -115,6 +115,16 @@ typedef struct {
                                  * decreases; counted in info.bad_index.  Column indices and
                                  * row_ptr[0] = 0, row_ptr[m] = nnz are always checked. */
 #define RLU_FLAG_TIMING 2u    /* record HIP events around each stage (rlu_stage_times) */
+#define RLU_FLAG_EXCLUSIVE 4u /* the caller guarantees that no other work runs on the device
+                               * while this call's kernels run.  The LU panel kernels, whose
+                               * blocks wait for each other, are then ordinary launches (on an
+                               * otherwise idle device every block is resident at once) rather
+                               * than cooperative launches, which guarantee co-residency under
+                               * any load but leave the device idle for about 11 us on each
+                               * side of every panel (8 panels at l = 210).  If other work does
+                               * keep some blocks from starting, the exchange gives up after
+                               * 2 s and the call reports RLU_ERR_DEVICE with info.timeouts > 0;
+                               * it does not hang.  Not accepted for served requests. */
 
 /* Stages reported by rlu_stage_times, in order. */
 enum {

@@ -35,6 +35,7 @@ RLU_F64, RLU_F32 = 0, 1
 PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2}
 RLU_FLAG_VALIDATE = 1
 RLU_FLAG_TIMING = 2
+RLU_FLAG_EXCLUSIVE = 4
 STAGES = ["params", "sketch", "lu_y", "contract", "gram", "chol", "solve", "lu_b", "assemble"]
 
 

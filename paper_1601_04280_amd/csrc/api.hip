@@ -69,7 +69,7 @@ rlu_status validate_params(const rlu_matrix *A, const rlu_params *p) {
   }
   if (p->l > kMaxL) return fail(RLU_ERR_INVALID_ARG, "l (%d) exceeds the supported maximum %d", p->l, kMaxL);
   if (p->precision < RLU_PREC_F64 || p->precision > RLU_PREC_BF16_REFINED) return fail(RLU_ERR_INVALID_ARG, "unknown precision %d", p->precision);
-  if (p->flags & ~(RLU_FLAG_VALIDATE | RLU_FLAG_TIMING)) return fail(RLU_ERR_INVALID_ARG, "unknown flag bits 0x%x", p->flags);
+  if (p->flags & ~(RLU_FLAG_VALIDATE | RLU_FLAG_TIMING | RLU_FLAG_EXCLUSIVE)) return fail(RLU_ERR_INVALID_ARG, "unknown flag bits 0x%x", p->flags);
   return RLU_OK;
 }
 
@@ -284,8 +284,9 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   double *Lhat = at<double>(ws, fp.Lhat);
   double *Uy = out->Uy ? out->Uy : at<double>(ws, fp.Uy);
   sm.begin(RLU_STAGE_LU_Y, st);
+  const bool exclusive = (p->flags & RLU_FLAG_EXCLUSIVE) != 0;
   e = launch_gepp(m, l, Y, ldy, Lhat, Uy, out->perm_r, out->ipiv_r, at<void>(ws, fp.slots), abort_flag, info,
-                  0, fp.py, st);
+                  0, fp.py, exclusive, st);
   if (e != hipSuccess) return hip_fail(e, "row-pivoted LU launch");
   sm.end(RLU_STAGE_LU_Y, st);
 
@@ -370,7 +371,7 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   double *Lph = at<double>(ws, fp.Lph), *Up = at<double>(ws, fp.Up), *Lt = at<double>(ws, fp.Lt);
   sm.begin(RLU_STAGE_LU_B, st);
   e = launch_gepp(n, l, Bt, l, Lph, Up, out->perm_c, out->ipiv_c, at<void>(ws, fp.slots), abort_flag, info, 1,
-                  fp.pb, st);
+                  fp.pb, exclusive, st);
   if (e != hipSuccess) return hip_fail(e, "column-pivoted LU launch");
   sm.end(RLU_STAGE_LU_B, st);
   sm.begin(RLU_STAGE_ASSEMBLE, st);
@@ -563,7 +564,7 @@ rlu_status rlu_tall_lu(rlu_ctx *ctx, const double *X, int64_t rows, int64_t cols
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(info), 0u, sizeof(rlu_info) / 4, s)) != hipSuccess)
     return hip_fail(e, "fill");
   e = launch_gepp(rows, (int)cols, X, ldx, Lhat, U, perm, ipiv, at<void>(ws, o_slots),
-                  reinterpret_cast<int32_t *>(ctl + 1), info, 0, gp, s);
+                  reinterpret_cast<int32_t *>(ctl + 1), info, 0, gp, false, s);
   if (e != hipSuccess) return hip_fail(e, "tall LU launch");
   if ((e = launch_finalize(info, reinterpret_cast<int32_t *>(ctl + 1), s)) != hipSuccess) return hip_fail(e, "finalize");
   return RLU_OK;

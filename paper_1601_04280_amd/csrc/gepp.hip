@@ -602,7 +602,7 @@ size_t gepp_workspace_bytes(int64_t rows, int cols, const GeppPlan &plan) {
 
 hipError_t launch_gepp(int64_t rows, int cols, const double *X, int64_t ldx, double *Lhat, double *U,
                        int32_t *perm, int32_t *ipiv, void *ws, int32_t *abort_flag, rlu_info *info,
-                       int which, const GeppPlan &plan, hipStream_t st) {
+                       int which, const GeppPlan &plan, bool exclusive, hipStream_t st) {
   GeppKernel k = gepp_kernel(64 / plan.nb);
   if (!k) return hipErrorInvalidValue;
   char *w = reinterpret_cast<char *>(ws);
@@ -648,7 +648,10 @@ hipError_t launch_gepp(int64_t rows, int cols, const double *X, int64_t ldx, dou
     a.j0 = j0;
     a.nbp = nbp;
     void *args[] = {&a};
-    e = hipLaunchCooperativeKernel((const void *)k, dim3(plan.G), dim3(kGeppThreads), args, 0, st);
+    // the blocks wait for each other: co-resident by a cooperative launch, or
+    // by the caller's guarantee that nothing else occupies the device
+    e = exclusive ? hipLaunchKernel((const void *)k, dim3(plan.G), dim3(kGeppThreads), args, 0, st)
+                  : hipLaunchCooperativeKernel((const void *)k, dim3(plan.G), dim3(kGeppThreads), args, 0, st);
     if (e != hipSuccess) return e;
     if (j1 >= cols) break;
     const int J2 = cols - j1;

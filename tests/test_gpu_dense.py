@@ -212,6 +212,23 @@ def test_factor_shapes(m, n, k, l, s):
     compare_factors(A, g, o)
 
 
+@pytest.mark.parametrize("m,n,k,l,s", [(3072, 1280, 100, 210, 512), (900, 300, 10, 35, 64)])
+def test_factor_exclusive_launch_matches(m, n, k, l, s):
+    # ordinary launches of the LU panels (the caller owns the device) run the
+    # same kernels as the cooperative ones.  Two runs agree to rounding only
+    # (the dense sketch's bucket sums are LDS atomics, in arrival order), so
+    # pivots must match exactly and values to the FP64 bar
+    A = to_dev(np.random.default_rng(m * n).standard_normal((m, n)))
+    a = rlu.factor(A, k=k, l=l, s=s, seed=7, keep_intermediates=True)
+    b = rlu.factor(A, k=k, l=l, s=s, seed=7, keep_intermediates=True, flags=rlu.RLU_FLAG_EXCLUSIVE)
+    torch.cuda.synchronize()
+    for name in ("perm_r", "perm_c", "ipiv_r", "ipiv_c"):
+        assert torch.equal(getattr(a, name), getattr(b, name)), name
+    for name in ("L", "U", "Y", "Uy", "B"):
+        assert rel_fro(getattr(a, name).cpu().numpy(), getattr(b, name).cpu().numpy()) <= 1e-10, name
+    assert b.info_dict()["status"] == 0
+
+
 @pytest.mark.parametrize("m,n,l,s", [(16, 16, 16, 16), (900, 35, 35, 64)])
 def test_factor_degenerate_sketch_properties(m, n, l, s):
     # l = n <= s: hash collisions leave empty buckets, so Y is exactly rank

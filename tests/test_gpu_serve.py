@@ -112,6 +112,8 @@ def test_serving_errors():
     assert lib.rlu_serve_start(ctx.handle, 1 << 30, 2) == 0
     pt = rlu._params(20, 30, 64, 1, flags=rlu.RLU_FLAG_TIMING)
     assert lib.rlu_submit(ctx.handle, ctypes.byref(mat), ctypes.byref(pt), ctypes.byref(f), ctypes.byref(t)) == 1
+    px = rlu._params(20, 30, 64, 1, flags=rlu.RLU_FLAG_EXCLUSIVE)      # requests share the device
+    assert lib.rlu_submit(ctx.handle, ctypes.byref(mat), ctypes.byref(px), ctypes.byref(f), ctypes.byref(t)) == 1
     assert lib.rlu_submit(ctx.handle, ctypes.byref(mat), ctypes.byref(p), ctypes.byref(f), ctypes.byref(t)) == 0
     assert lib.rlu_serve_stop(ctx.handle) == 0                         # waits for the request
     assert lib.rlu_poll(ctx.handle, t.value) == 6                      # stopped: tickets gone
