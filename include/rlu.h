@@ -125,6 +125,9 @@ typedef struct {
                                * keep some blocks from starting, the exchange gives up after
                                * 2 s and the call reports RLU_ERR_DEVICE with info.timeouts > 0;
                                * it does not hang.  Not accepted for served requests. */
+#define RLU_FLAG_TIMING_CONTRACT 8u /* events around the contraction stage only (one stage
+                                     * boundary instead of nine; rlu_stage_times reports the
+                                     * other stages as 0 for such calls) */
 
 /* Stages reported by rlu_stage_times, in order. */
 enum {
@@ -202,9 +205,10 @@ rlu_status rlu_tall_lu(rlu_ctx *ctx, const double *X, int64_t rows, int64_t cols
 rlu_status rlu_tall_lu_workspace_size(rlu_ctx *ctx, int64_t rows, int64_t cols, size_t *bytes);
 
 /* Per-stage device milliseconds (HIP events at each stage's start and end)
- * summed over every rlu_factor call made with RLU_FLAG_TIMING on this context
- * since the previous rlu_stage_times call (which waits for those events and
- * then clears them).  For a sparse A, or a contraction of at least 1e11
+ * summed over every rlu_factor call made with RLU_FLAG_TIMING (all stages) or
+ * RLU_FLAG_TIMING_CONTRACT (the contraction only; 0 for its other stages) on
+ * this context since the previous rlu_stage_times call (which waits for those
+ * events and then clears them).  For a sparse A, or a contraction of at least 1e11
  * multiply-adds (m n l), the Gram and Cholesky stages run on a second stream
  * beside the contraction: their intervals then overlap it, and the stage
  * times add up to more than the call.

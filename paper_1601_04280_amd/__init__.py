@@ -36,6 +36,7 @@ PRECISIONS = {"f64": 0, "f32": 1, "bf16": 2}
 RLU_FLAG_VALIDATE = 1
 RLU_FLAG_TIMING = 2
 RLU_FLAG_EXCLUSIVE = 4
+RLU_FLAG_TIMING_CONTRACT = 8
 STAGES = ["params", "sketch", "lu_y", "contract", "gram", "chol", "solve", "lu_b", "assemble"]
 
 
@@ -155,7 +156,8 @@ class Context:
         return base + off, self._ws.numel() - off
 
     def stage_times(self):
-        """{stage: total ms} over calls made with RLU_FLAG_TIMING since the last read, and the call count."""
+        """{stage: total ms} over calls made with RLU_FLAG_TIMING (or RLU_FLAG_TIMING_CONTRACT: the
+        contraction only) since the last read, and the call count."""
         ms = (ctypes.c_float * len(STAGES))()
         calls = ctypes.c_int(0)
         _check(load_library().rlu_stage_times(self._h, ms, ctypes.byref(calls)))

@@ -69,7 +69,7 @@ rlu_status validate_params(const rlu_matrix *A, const rlu_params *p) {
   }
   if (p->l > kMaxL) return fail(RLU_ERR_INVALID_ARG, "l (%d) exceeds the supported maximum %d", p->l, kMaxL);
   if (p->precision < RLU_PREC_F64 || p->precision > RLU_PREC_BF16_REFINED) return fail(RLU_ERR_INVALID_ARG, "unknown precision %d", p->precision);
-  if (p->flags & ~(RLU_FLAG_VALIDATE | RLU_FLAG_TIMING | RLU_FLAG_EXCLUSIVE)) return fail(RLU_ERR_INVALID_ARG, "unknown flag bits 0x%x", p->flags);
+  if (p->flags & ~(RLU_FLAG_VALIDATE | RLU_FLAG_TIMING | RLU_FLAG_EXCLUSIVE | RLU_FLAG_TIMING_CONTRACT)) return fail(RLU_ERR_INVALID_ARG, "unknown flag bits 0x%x", p->flags);
   return RLU_OK;
 }
 
@@ -187,19 +187,20 @@ static rlu_status run_sketch(const rlu_ctx_impl &cx, const FactorPlan &fp, const
   return e == hipSuccess ? RLU_OK : hip_fail(e, "sketch kernel");
 }
 
-// Start / end events of every stage of one timed call (no-ops when timing is off).
+// Start / end events of the recorded stages of one timed call (no-ops when
+// timing is off): every stage, or the contraction only.
 struct StageMarks {
   std::array<hipEvent_t, 2 * RLU_NUM_STAGES> ev{};
-  bool on = false;
+  uint32_t mask = 0;  // bit i: stage i recorded
   void begin(int i, hipStream_t s) {
-    if (on) hipEventRecord(ev[2 * i], s);
+    if (mask >> i & 1) hipEventRecord(ev[2 * i], s);
   }
   void end(int i, hipStream_t s) {
-    if (on) hipEventRecord(ev[2 * i + 1], s);
+    if (mask >> i & 1) hipEventRecord(ev[2 * i + 1], s);
   }
 };
 
-static rlu_status begin_timing(rlu_ctx_impl &cx, StageMarks &sm) {
+static rlu_status begin_timing(rlu_ctx_impl &cx, StageMarks &sm, uint32_t mask) {
   StageTimer &t = cx.timer;
   while (t.pool.size() < t.used + 2 * RLU_NUM_STAGES) {
     // timing only (read after the caller synchronises): no system-scope
@@ -211,8 +212,8 @@ static rlu_status begin_timing(rlu_ctx_impl &cx, StageMarks &sm) {
   }
   for (int i = 0; i < 2 * RLU_NUM_STAGES; ++i) sm.ev[i] = t.pool[t.used + i];
   t.used += 2 * RLU_NUM_STAGES;
-  t.calls.push_back(sm.ev);
-  sm.on = true;
+  t.calls.push_back({sm.ev, mask});
+  sm.mask = mask;
   return RLU_OK;
 }
 
@@ -256,8 +257,9 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   const int l = p->l;
   hipError_t e;
   StageMarks sm;
-  if (p->flags & RLU_FLAG_TIMING) {
-    rlu_status ts = begin_timing(cx, sm);
+  if (p->flags & (RLU_FLAG_TIMING | RLU_FLAG_TIMING_CONTRACT)) {
+    const uint32_t mask = (p->flags & RLU_FLAG_TIMING) ? (1u << RLU_NUM_STAGES) - 1 : 1u << RLU_STAGE_CONTRACT;
+    rlu_status ts = begin_timing(cx, sm, mask);
     if (ts != RLU_OK) return ts;
   }
   AuxStream ax;
@@ -509,8 +511,10 @@ rlu_status rlu_stage_times(rlu_ctx *ctx, float *ms, int *calls) {
   rlu_ctx_impl &cx = *reinterpret_cast<rlu_ctx_impl *>(ctx);
   for (int i = 0; i < RLU_NUM_STAGES; ++i) ms[i] = 0.f;
   StageTimer &t = cx.timer;
-  for (auto &ev : t.calls) {
+  for (auto &call : t.calls) {
+    const auto &ev = call.ev;
     for (int i = 0; i < RLU_NUM_STAGES; ++i) {
+      if (!(call.mask >> i & 1)) continue;
       hipError_t e = hipEventSynchronize(ev[2 * i + 1]);
       if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
       float v = 0.f;

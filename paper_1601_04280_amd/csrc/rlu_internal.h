@@ -142,7 +142,11 @@ struct ServeState;
 struct StageTimer {
   std::vector<hipEvent_t> pool;
   size_t used = 0;
-  std::vector<std::array<hipEvent_t, 2 * RLU_NUM_STAGES>> calls;
+  struct Call {
+    std::array<hipEvent_t, 2 * RLU_NUM_STAGES> ev;
+    uint32_t mask;  // stages recorded
+  };
+  std::vector<Call> calls;
 };
 // A second stream per caller stream: the Gram matrix, its Cholesky factor and
 // G^{-1} depend only on Lhat and run there while the contraction runs on the

@@ -218,7 +218,8 @@ rlu_status rlu_submit(rlu_ctx *ctx, const rlu_matrix *A, const rlu_params *p, co
   if (st != RLU_OK) return st;
   if ((st = validate_params(A, p)) != RLU_OK) return st;
   if ((st = validate_factors(A, p, out)) != RLU_OK) return st;
-  if (p->flags & RLU_FLAG_TIMING) return fail(RLU_ERR_INVALID_ARG, "RLU_FLAG_TIMING is not available for served requests");
+  if (p->flags & (RLU_FLAG_TIMING | RLU_FLAG_TIMING_CONTRACT))
+    return fail(RLU_ERR_INVALID_ARG, "stage timing is not available for served requests");
   if (p->flags & RLU_FLAG_EXCLUSIVE)  // requests in flight share the device by design
     return fail(RLU_ERR_INVALID_ARG, "RLU_FLAG_EXCLUSIVE is not available for served requests");
   ServeRequest r;

@@ -229,6 +229,25 @@ def test_factor_exclusive_launch_matches(m, n, k, l, s):
     assert b.info_dict()["status"] == 0
 
 
+def test_stage_times_all_or_contraction_only():
+    A = to_dev(np.random.default_rng(3).standard_normal((2048, 1024)))
+    ctx = rlu.Context(0)
+    kw = dict(k=50, l=100, s=256, seed=2, ctx=ctx)
+    out = rlu.factor(A, **kw)
+    ctx.stage_times()
+    for _ in range(2):
+        rlu.factor(A, out=out, flags=rlu.RLU_FLAG_TIMING, **kw)
+    full, calls = ctx.stage_times()
+    assert calls == 2 and all(v > 0 for v in full.values()), full
+    for _ in range(3):
+        rlu.factor(A, out=out, flags=rlu.RLU_FLAG_TIMING_CONTRACT | rlu.RLU_FLAG_EXCLUSIVE, **kw)
+    only, calls = ctx.stage_times()
+    assert calls == 3 and only["contract"] > 0
+    assert all(v == 0 for k, v in only.items() if k != "contract"), only
+    assert ctx.stage_times() == ({k: 0.0 for k in full}, 0)    # cleared by the read
+    ctx.close()
+
+
 @pytest.mark.parametrize("m,n,l,s", [(16, 16, 16, 16), (900, 35, 35, 64)])
 def test_factor_degenerate_sketch_properties(m, n, l, s):
     # l = n <= s: hash collisions leave empty buckets, so Y is exactly rank
