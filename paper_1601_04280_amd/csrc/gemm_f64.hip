@@ -226,6 +226,9 @@ __global__ __launch_bounds__(128 * WGM, 1) void k_gemm(GemmK p) {
 // lds + 16 i).  A plain device function: the builtin exists only for the
 // device, and the kernel template must also instantiate in the host pass.
 __device__ inline void lds_copy16(const double *g, double *lds) { __builtin_amdgcn_global_load_lds(g, lds, 16, 0, 0); }
+// the same with the nontemporal hint (cache policy bit 1), for an operand
+// that every element of is read once per launch
+__device__ inline void lds_copy16_nt(const double *g, double *lds) { __builtin_amdgcn_global_load_lds(g, lds, 16, 0, 2); }
 
 template <int FN>
 __global__ __launch_bounds__(512, 1) void k_gemm_dma(GemmK p) {
@@ -267,7 +270,7 @@ __global__ __launch_bounds__(512, 1) void k_gemm_dma(GemmK p) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int kr = 2 * wave + q;
-      lds_copy16(uniform_ptr(A + (k0 + kr) * p.lda + m0) + 2 * lane, as + kr * AS);
+      lds_copy16_nt(uniform_ptr(A + (k0 + kr) * p.lda + m0) + 2 * lane, as + kr * AS);
       const double *brow = uniform_ptr(B + (k0 + kr) * p.ldb + n0);
 #pragma unroll
       for (int h = 0; h < H; ++h) {

@@ -341,7 +341,7 @@ __global__ __launch_bounds__(kWsThreads, 4) void k_sketch_ws(int64_t m, int64_t 
     for (int u = 0; u < U; ++u) {  // 32-bit offsets from uniform bases; clamped, masked when scattered
       const uint32_t e = (uint32_t)(u * kWsSem + tx) * W;
       const uint32_t ee = e < nj ? e : 0;
-      v[u] = *reinterpret_cast<const VT *>(aj + ee);
+      v[u] = __builtin_nontemporal_load(reinterpret_cast<const VT *>(aj + ee));  // A: read once
       c[u] = *reinterpret_cast<const CT *>(cj + ee);
     }
   };
