@@ -418,7 +418,7 @@ __global__ __launch_bounds__(256) void k_bf16_resid(Bf16Resid p) {
         const int64_t row = m0 + wm * 16 * WM + i * 16 + 4 * (lane >> 4) + v;
         const int64_t col = n0 + wn * 16 * WN + j * 16 + (lane & 15);
         const bool ok = row < p.M && col < p.N;
-        av[i][j][v] = A[(ok ? row : m0) * p.lda + (ok ? col : n0)];
+        av[i][j][v] = __builtin_nontemporal_load(A + (ok ? row : m0) * p.lda + (ok ? col : n0));  // read once
       }
 #pragma unroll
   for (int i = 0; i < WM; ++i)

@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kSketchThreads) void k_sketch_dense(
     for (int u = 0; u < PF; ++u) {
       const int64_t j = tid + (int64_t)u * TH;
       const int64_t jj = j < n ? j : 0;
-      pv[u] = a[jj];
+      pv[u] = __builtin_nontemporal_load(a + jj);  // A: read once
       pc[u] = code[jj];
     }
   };
@@ -84,13 +84,13 @@ __global__ __launch_bounds__(kSketchThreads) void k_sketch_dense(
       T v[U];
       uint32_t c[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) { v[u] = a[j + u * TH]; c[u] = code[j + u * TH]; }
+      for (int u = 0; u < U; ++u) { v[u] = __builtin_nontemporal_load(a + j + u * TH); c[u] = code[j + u * TH]; }
 #pragma unroll
       for (int u = 0; u < U; ++u) atomicAdd(&y0[code_bucket(c[u])], code_apply(c[u], to_f64(v[u])));
     }
     for (; j < n; j += TH) {
       const uint32_t c = code[j];
-      atomicAdd(&y0[code_bucket(c)], code_apply(c, to_f64(a[j])));
+      atomicAdd(&y0[code_bucket(c)], code_apply(c, to_f64(__builtin_nontemporal_load(a + j))));
     }
     __syncthreads();
     if (row + gridDim.x < m) prefetch(row + gridDim.x);  // in flight during the transform
