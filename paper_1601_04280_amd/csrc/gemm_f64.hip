@@ -380,8 +380,18 @@ __global__ void k_splitk_reduce(int64_t M, int64_t N, int splits, const double *
   const int64_t total = M * N;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
+    // partials in order 0, 1, 2, ... (a fixed summation order); eight loads
+    // in flight at a time
     double s = 0.0;
-    for (int z = 0; z < splits; ++z) s += parts[(int64_t)z * total + e];
+    int z = 0;
+    for (; z + 8 <= splits; z += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = parts[(int64_t)(z + u) * total + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; z < splits; ++z) s += parts[(int64_t)z * total + e];
     const int64_t m = e / N, n = e - m * N;
     double r = alpha * s;
     if (beta != 0.0) r += beta * C[m * ldc + n];
