@@ -24,6 +24,7 @@ class Params:
     l: int
     s: int
     seed: int
+    transform: str = "fourier"   # or "hadamard": the FJL's T (see sketch.py)
 
 
 @dataclass
@@ -71,11 +72,11 @@ def sketch_y(A, p: Params, csr=None):
         row_ptr, col, val, m, n = csr
         check_params(m, n, p)
         h, sgn, d, sel = sketch_params(n, p)
-        return sk.sketch_csr(row_ptr, col, val, m, n, h, sgn, d, sel, p.s)
+        return sk.sketch_csr(row_ptr, col, val, m, n, h, sgn, d, sel, p.s, p.transform)
     A = np.asarray(A, dtype=np.float64)
     check_params(*A.shape, p)
     h, sgn, d, sel = sketch_params(A.shape[1], p)
-    return sk.sketch_dense(A, h, sgn, d, sel, p.s)
+    return sk.sketch_dense(A, h, sgn, d, sel, p.s, p.transform)
 
 
 def rlu(A, p: Params, csr=None) -> Result:

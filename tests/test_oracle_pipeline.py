@@ -96,3 +96,9 @@ def test_factors_reassemble_steps():
 def test_invalid_params(bad):
     with pytest.raises(ValueError):
         R.check_params(60, 50, R.Params(seed=1, **bad))
+
+
+def test_rank_exact_input_is_reproduced_with_hadamard():
+    A = synth.lowrank_dense(400, 300, np.linspace(1.0, 0.1, 15), 3)
+    res = R.rlu(A, R.Params(15, 20, 64, 7, "hadamard"))
+    assert R.residual_fro(A, res.L, res.U, res.perm_r, res.perm_c) <= 1e-12 * np.linalg.norm(A)

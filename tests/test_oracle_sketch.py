@@ -129,3 +129,49 @@ def test_srft_embedding_theorem():
         sv = np.linalg.svd(M, compute_uv=False)
         ok += (sv.min() >= 0.40) and (sv.max() <= 1.48)
     assert ok >= 36
+
+
+# ---- the Walsh-Hadamard form of the transform (the paper's Section 4 choice)
+
+@pytest.mark.parametrize("s", [1, 2, 4, 16, 256, 2048])
+def test_hadamard_matches_sylvester_construction(s):
+    import scipy.linalg as sl
+    H = sketch.hadamard_columns(s, np.arange(s))
+    np.testing.assert_array_equal(H, sl.hadamard(s))         # Sylvester order
+    np.testing.assert_array_equal(H @ H.T, s * np.eye(s))      # H H^T = s I
+    cols = np.array([s - 1, 0, s // 2]) if s > 1 else np.array([0])
+    np.testing.assert_array_equal(sketch.hadamard_columns(s, cols), sl.hadamard(s)[:, cols])
+
+
+def test_hadamard_transform_hand_worked():
+    # s = 2: z = Y0 diag(d) = [3, -1]; z H_2 / sqrt 2 = [2, 4] / sqrt 2; sel = (1, 0)
+    y = sketch.fjl_apply(np.array([[3.0, 1.0]]), np.array([1.0, -1.0]), np.array([1, 0]), "hadamard")
+    np.testing.assert_allclose(y, [[4.0 / np.sqrt(2.0), 2.0 / np.sqrt(2.0)]], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("s", [8, 128])
+def test_hadamard_transform_orthonormal(s):
+    # every coordinate kept: an orthogonal transform keeps the row norms
+    y0 = np.random.default_rng(s).standard_normal((5, s))
+    d = rng.srft_signs(3, s)
+    y = sketch.fjl_apply(y0, d, np.arange(s), "hadamard")
+    np.testing.assert_allclose(np.linalg.norm(y, axis=1), np.linalg.norm(y0, axis=1), rtol=1e-13)
+
+
+@pytest.mark.parametrize("m,n,s,l", [(6, 50, 16, 5), (20, 300, 64, 12)])
+def test_hadamard_sketch_brute_force(m, n, s, l):
+    # Y = A S^T diag(d) (H / sqrt s) R with every operator an explicit matrix
+    import scipy.linalg as sl
+    a = np.random.default_rng(6).standard_normal((m, n))
+    seed = 22
+    h, sgn = rng.sem_hash(seed, n, s)
+    d = rng.srft_signs(seed, s)
+    sel = rng.srft_select(seed, s, l)
+    R = np.zeros((s, l))
+    R[sel, np.arange(l)] = 1.0
+    omega_t = explicit_sem(h, sgn, s).T @ np.diag(d) @ (sl.hadamard(s) / np.sqrt(s)) @ R
+    y = sketch.sketch_dense(a, h, sgn, d, sel, s, "hadamard")
+    np.testing.assert_allclose(y, a @ omega_t, rtol=1e-12, atol=1e-12)
+    csr = sp.csr_matrix(a)
+    yc = sketch.sketch_csr(csr.indptr, csr.indices, csr.data, m, n, h, sgn, d, sel, s, "hadamard")
+    np.testing.assert_allclose(yc, a @ omega_t, rtol=1e-12, atol=1e-12)
