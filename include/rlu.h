@@ -125,6 +125,11 @@ typedef struct {
                                * keep some blocks from starting, the exchange gives up after
                                * 2 s and the call reports RLU_ERR_DEVICE with info.timeouts > 0;
                                * it does not hang.  Not accepted for served requests. */
+#define RLU_FLAG_HADAMARD 16u  /* the sketch's transform T is the Walsh-Hadamard matrix
+                                * H_s / sqrt(s) in Sylvester order, H[b][c] = (-1)^popcount(b & c)
+                                * (the subsampled randomized Hadamard transform of Section 4),
+                                * instead of the orthonormal real Fourier transform; the
+                                * signs, the selection and the sparse embedding are the same */
 #define RLU_FLAG_TIMING_CONTRACT 8u /* events around the contraction stage only (one stage
                                      * boundary instead of nine; rlu_stage_times reports the
                                      * other stages as 0 for such calls) */

@@ -37,6 +37,7 @@ RLU_FLAG_VALIDATE = 1
 RLU_FLAG_TIMING = 2
 RLU_FLAG_EXCLUSIVE = 4
 RLU_FLAG_TIMING_CONTRACT = 8
+RLU_FLAG_HADAMARD = 16
 STAGES = ["params", "sketch", "lu_y", "contract", "gram", "chol", "solve", "lu_b", "assemble"]
 
 
@@ -227,12 +228,13 @@ def sketch_params(n: int, l: int, s: int, seed: int, device: int = 0):
     return h, sgn, d, sel
 
 
-def sketch(A=None, *, k: int, l: int, s: int, seed: int, csr=None, ctx: Context = None, Y=None):
-    """Algorithm 1 steps 1-2: Y = A Omega_1^T on the device (m x l, float64)."""
+def sketch(A=None, *, k: int, l: int, s: int, seed: int, csr=None, ctx: Context = None, Y=None, flags: int = 0):
+    """Algorithm 1 steps 1-2: Y = A Omega_1^T on the device (m x l, float64).
+    flags: RLU_FLAG_* (RLU_FLAG_HADAMARD for the Walsh-Hadamard transform)."""
     torch = _torch()
     ctx = ctx or default_context()
     mat = _dense_matrix(A) if csr is None else _csr_matrix(*csr)
-    p = _params(k, l, s, seed)
+    p = _params(k, l, s, seed, flags=flags)
     lib = load_library()
     nbytes = ctypes.c_size_t()
     _check(lib.rlu_workspace_size(ctx.handle, ctypes.byref(mat), ctypes.byref(p), ctypes.byref(nbytes)))

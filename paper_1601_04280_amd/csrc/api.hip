@@ -69,7 +69,8 @@ rlu_status validate_params(const rlu_matrix *A, const rlu_params *p) {
   }
   if (p->l > kMaxL) return fail(RLU_ERR_INVALID_ARG, "l (%d) exceeds the supported maximum %d", p->l, kMaxL);
   if (p->precision < RLU_PREC_F64 || p->precision > RLU_PREC_BF16_REFINED) return fail(RLU_ERR_INVALID_ARG, "unknown precision %d", p->precision);
-  if (p->flags & ~(RLU_FLAG_VALIDATE | RLU_FLAG_TIMING | RLU_FLAG_EXCLUSIVE | RLU_FLAG_TIMING_CONTRACT)) return fail(RLU_ERR_INVALID_ARG, "unknown flag bits 0x%x", p->flags);
+  if (p->flags & ~(RLU_FLAG_VALIDATE | RLU_FLAG_TIMING | RLU_FLAG_EXCLUSIVE | RLU_FLAG_TIMING_CONTRACT |
+                   RLU_FLAG_HADAMARD)) return fail(RLU_ERR_INVALID_ARG, "unknown flag bits 0x%x", p->flags);
   return RLU_OK;
 }
 
@@ -173,7 +174,7 @@ static rlu_status run_sketch(const rlu_ctx_impl &cx, const FactorPlan &fp, const
   if (A->layout == RLU_DENSE_ROW_MAJOR) {
     e = launch_sketch_dense(A->m, A->n, A->values, A->dtype, A->ld, p->s, p->l, at<uint32_t>(ws, fp.code),
                             at<int32_t>(ws, fp.sel), at<double2>(ws, fp.twf), at<double2>(ws, fp.twp),
-                            Y, ldy, at<uint32_t>(ws, fp.ctl) + 3, cx.caps.num_cu, st);
+                            Y, ldy, at<uint32_t>(ws, fp.ctl) + 3, cx.caps.num_cu, (p->flags & RLU_FLAG_HADAMARD) != 0, st);
   } else {
     if (info) {
       e = launch_csr_check(A, (p->flags & RLU_FLAG_VALIDATE) != 0, info, st);
@@ -182,7 +183,7 @@ static rlu_status run_sketch(const rlu_ctx_impl &cx, const FactorPlan &fp, const
     e = launch_sketch_csr(A->m, A->n, A->row_ptr, A->col_idx, (const double *)A->values, A->nnz, p->s, p->l,
                           at<uint32_t>(ws, fp.code), at<int32_t>(ws, fp.sel), at<double2>(ws, fp.twf),
                           at<double2>(ws, fp.twp), Y, ldy, info ? &info->bad_index : at<int32_t>(ws, fp.ctl) + 2,
-                          cx.caps.num_cu, st);
+                          cx.caps.num_cu, (p->flags & RLU_FLAG_HADAMARD) != 0, st);
   }
   return e == hipSuccess ? RLU_OK : hip_fail(e, "sketch kernel");
 }

@@ -35,15 +35,17 @@ void launch_srft_params(int s, int l, uint64_t seed, int8_t *d, int32_t *sel, do
 struct SketchPlan {
   int grid;  // blocks of the dense sketch
 };
-// row_counter: one word, zero on entry (rows are handed out through it)
+// row_counter: one word, zero on entry (rows are handed out through it).
+// hadamard: the transform is H_s / sqrt(s) (Sylvester order) instead of the
+// orthonormal real Fourier transform
 hipError_t launch_sketch_dense(int64_t m, int64_t n, const void *A, int dtype, int64_t lda, int s,
                                int l, const uint32_t *code, const int32_t *sel,
                                const double2 *twf, const double2 *twp, double *Y, int64_t ldy,
-                               uint32_t *row_counter, int num_cu, hipStream_t st);
+                               uint32_t *row_counter, int num_cu, bool hadamard, hipStream_t st);
 hipError_t launch_sketch_csr(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t *col,
                              const double *val, int64_t nnz, int s, int l, const uint32_t *code,
                              const int32_t *sel, const double2 *twf, const double2 *twp, double *Y,
-                             int64_t ldy, int32_t *bad_index, int num_cu, hipStream_t st);
+                             int64_t ldy, int32_t *bad_index, int num_cu, bool hadamard, hipStream_t st);
 hipError_t launch_csr_check(const rlu_matrix *A, int validate_rows, rlu_info *info, hipStream_t st);
 size_t csc_scratch_bytes(int64_t n, int64_t nnz);
 // W^T (n x l) = A^T Lhat for CSR A, through a CSC copy built in `scratch`

@@ -13,6 +13,8 @@
 // SEM sign folded with the transform's diagonal, as in the dense kernel.
 // Cost 2 nnz l flops; one wavefront per row, each lane a few outputs, the
 // row's nonzeros broadcast lane by lane, cos(2 pi k / s) from an LDS table.
+// With the Walsh-Hadamard transform (HAD) the kernel is the sign
+// (-1)^popcount(b & sel[q]) and the weight 1/sqrt s.
 //
 // Contraction.  A^T is built once per call as CSC (column counts, scan,
 // scatter with atomic cursors); one wavefront per column then gathers rows of
@@ -30,7 +32,7 @@ __device__ inline int64_t clamp_ptr(int32_t p, int64_t nnz) {
   return p < 0 ? 0 : (p > nnz ? nnz : (int64_t)p);
 }
 
-template <int QPL>
+template <int QPL, bool HAD>
 __global__ __launch_bounds__(256) void k_sketch_csr(int64_t m, int64_t n, int64_t nnz,
                                                     const int32_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ col,
@@ -53,7 +55,8 @@ __global__ __launch_bounds__(256) void k_sketch_csr(int64_t m, int64_t n, int64_
   for (int t = 0; t < QPL; ++t) {
     const int q = lane + 64 * t;
     const int f = q < l ? sel[q] : 0;
-    if (f == 0) { qa[t] = 0; qo[t] = 0; qw[t] = rs; }
+    if (HAD) { qa[t] = (uint32_t)f; qo[t] = 0; qw[t] = rs; }
+    else if (f == 0) { qa[t] = 0; qo[t] = 0; qw[t] = rs; }
     else if (f == N) { qa[t] = (uint32_t)N; qo[t] = 0; qw[t] = rs; }
     else if (f < N) { qa[t] = (uint32_t)f; qo[t] = 0; qw[t] = r2s; }
     else { qa[t] = (uint32_t)(s - f); qo[t] = (uint32_t)(3 * (s / 4)); qw[t] = -r2s; }
@@ -88,7 +91,10 @@ __global__ __launch_bounds__(256) void k_sketch_csr(int64_t m, int64_t n, int64_
         const int hi32 = __builtin_amdgcn_readlane((int)(uint32_t)(bits >> 32), e);
         const double ve = __longlong_as_double(((int64_t)(uint32_t)hi32 << 32) | (uint32_t)lo32);
 #pragma unroll
-        for (int t = 0; t < QPL; ++t) acc[t] += ve * ctab[(qa[t] * be + qo[t]) & mask];
+        for (int t = 0; t < QPL; ++t) {
+          if (HAD) acc[t] += (__popc(qa[t] & be) & 1) ? -ve : ve;
+          else acc[t] += ve * ctab[(qa[t] * be + qo[t]) & mask];
+        }
       }
     }
 #pragma unroll
@@ -103,15 +109,19 @@ __global__ __launch_bounds__(256) void k_sketch_csr(int64_t m, int64_t n, int64_
 hipError_t launch_sketch_csr(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t *col,
                              const double *val, int64_t nnz, int s, int l, const uint32_t *code,
                              const int32_t *sel, const double2 *twf, const double2 *twp, double *Y,
-                             int64_t ldy, int32_t *bad_index, int num_cu, hipStream_t st) {
+                             int64_t ldy, int32_t *bad_index, int num_cu, bool hadamard, hipStream_t st) {
   (void)twf;
   const int qpl = (int)ceil_div(l, 64);
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(m, 4), (int64_t)num_cu * 8));
   const size_t lds = (size_t)s * sizeof(double);
-#define RLU_CSR_Q(Q)                                                                                \
-  case Q:                                                                                           \
-    hipLaunchKernelGGL(k_sketch_csr<Q>, dim3(blocks), dim3(256), lds, st, m, n, nnz, row_ptr, col, \
-                       val, s, l, code, sel, twp, Y, ldy, bad_index);                               \
+#define RLU_CSR_Q(Q)                                                                                    \
+  case Q:                                                                                               \
+    if (hadamard)                                                                                       \
+      hipLaunchKernelGGL((k_sketch_csr<Q, true>), dim3(blocks), dim3(256), lds, st, m, n, nnz, row_ptr,  \
+                         col, val, s, l, code, sel, twp, Y, ldy, bad_index);                            \
+    else                                                                                                \
+      hipLaunchKernelGGL((k_sketch_csr<Q, false>), dim3(blocks), dim3(256), lds, st, m, n, nnz, row_ptr, \
+                         col, val, s, l, code, sel, twp, Y, ldy, bad_index);                            \
     break;
   switch (qpl) {
     RLU_CSR_Q(1) RLU_CSR_Q(2) RLU_CSR_Q(3) RLU_CSR_Q(4) RLU_CSR_Q(5) RLU_CSR_Q(6) RLU_CSR_Q(7)
@@ -123,8 +133,10 @@ hipError_t launch_sketch_csr(int64_t m, int64_t n, const int32_t *row_ptr, const
 }
 
 void sketch_csr_set_attrs() {
-#define RLU_CSR_A(Q) \
-  (void)hipFuncSetAttribute((const void *)k_sketch_csr<Q>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxS * 8);
+#define RLU_CSR_A(Q)                                                                                            \
+  (void)hipFuncSetAttribute((const void *)k_sketch_csr<Q, false>, hipFuncAttributeMaxDynamicSharedMemorySize,  \
+                            kMaxS * 8);                                                                          \
+  (void)hipFuncSetAttribute((const void *)k_sketch_csr<Q, true>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxS * 8);
   RLU_CSR_A(1) RLU_CSR_A(2) RLU_CSR_A(3) RLU_CSR_A(4) RLU_CSR_A(5) RLU_CSR_A(6) RLU_CSR_A(7) RLU_CSR_A(8)
   RLU_CSR_A(9)
 #undef RLU_CSR_A

@@ -27,12 +27,72 @@ static size_t sketch_lds_bytes(int s, int l) {
   return (size_t)(2 * N + 2 * (nlo + nhi)) * sizeof(double2) + (size_t)l * sizeof(int32_t);
 }
 
+// ---- Walsh-Hadamard form of the transform ------------------------------------
+// T = H_s / sqrt(s) with H in Sylvester order, H[b][c] = (-1)^popcount(b & c)
+// (the subsampled randomized Hadamard transform of the paper's experiments,
+// Section 4).  The unnormalised transform in place, in passes of up to four
+// butterfly stages held in registers: pass p pairs indices that differ in
+// bits 4p .. 4p + 3; a group is the 2^ns indices sharing every other bit.
+// The output stays in natural order, so coordinate c is read at position c.
+template <typename Idx>
+__device__ inline void fwht_group(double *z, int base, int stride, int ns, Idx idx) {
+  double v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (k < (1 << ns)) v[k] = z[idx(base + k * stride)];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (t < ns) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (!(k & (1 << t))) {
+          const double a = v[k], b = v[k | (1 << t)];
+          v[k] = a + b;
+          v[k | (1 << t)] = a - b;
+        }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k)
+    if (k < (1 << ns)) z[idx(base + k * stride)] = v[k];
+}
+
+// by one wave over a row buffer of the wave-specialised sketch (value b at
+// b + 2 (b >> 5)); the wave's LDS operations complete in order, so a pass
+// reads what the previous one wrote
+__device__ inline int wpad(int b) { return b + 2 * (b >> 5); }
+__device__ inline void fwht_wave(double *z, int log2s, int ln) {
+  const int s = 1 << log2s;
+  for (int st0 = 0; st0 < log2s; st0 += 4) {
+    const int ns = min(4, log2s - st0);
+    for (int gi = ln; gi < (s >> ns); gi += 64) {
+      const int base = ((gi >> st0) << (st0 + ns)) + (gi & ((1 << st0) - 1));
+      fwht_group(z, base, 1 << st0, ns, [](int b) { return wpad(b); });
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  }
+}
+
+// by a block of TH threads over an unpadded buffer, a barrier after each pass
+template <int TH>
+__device__ inline void fwht_block(double *z, int log2s, int tid) {
+  const int s = 1 << log2s;
+  for (int st0 = 0; st0 < log2s; st0 += 4) {
+    const int ns = min(4, log2s - st0);
+    for (int gi = tid; gi < (s >> ns); gi += TH) {
+      const int base = ((gi >> st0) << (st0 + ns)) + (gi & ((1 << st0) - 1));
+      fwht_group(z, base, 1 << st0, ns, [](int b) { return b; });
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T, int PF>
 __global__ __launch_bounds__(kSketchThreads) void k_sketch_dense(
     int64_t m, int64_t n, const T *__restrict__ A, int64_t lda, int s, int log2N, int l,
     const uint32_t *__restrict__ code, const int32_t *__restrict__ sel,
     const double2 *__restrict__ twf, const double2 *__restrict__ twp, double *__restrict__ Y,
-    int64_t ldy) {
+    int64_t ldy, int hadamard) {
   extern __shared__ double2 lds2[];
   constexpr int TH = kSketchThreads;
   constexpr int U = 16;
@@ -95,9 +155,14 @@ __global__ __launch_bounds__(kSketchThreads) void k_sketch_dense(
     __syncthreads();
     if (row + gridDim.x < m) prefetch(row + gridDim.x);  // in flight during the transform
 
-    const double2 *Z = fft_lds<TH>(buf, buf + N, N, log2N, tf);
     double *yrow = Y + row * ldy;
-    for (int q = tid; q < l; q += TH) yrow[q] = real_coord(Z, s, sel_s[q], tp, rs, r2s);
+    if (hadamard) {  // in place on the bucket sums, natural order
+      fwht_block<TH>(y0, log2N + 1, tid);
+      for (int q = tid; q < l; q += TH) yrow[q] = y0[sel_s[q]] * rs;
+    } else {
+      const double2 *Z = fft_lds<TH>(buf, buf + N, N, log2N, tf);
+      for (int q = tid; q < l; q += TH) yrow[q] = real_coord(Z, s, sel_s[q], tp, rs, r2s);
+    }
     __syncthreads();
   }
 }
@@ -282,7 +347,7 @@ __global__ __launch_bounds__(kWsThreads, 4) void k_sketch_ws(int64_t m, int64_t 
                                                           const int32_t *__restrict__ sel,
                                                           const double2 *__restrict__ twf,
                                                           const double2 *__restrict__ twp, double *__restrict__ Y,
-                                                          int64_t ldy, uint32_t *__restrict__ next_row) {
+                                                          int64_t ldy, uint32_t *__restrict__ next_row, int hadamard) {
   typedef typename WsVec<T>::V VT;
   typedef typename WsVec<T>::C CT;
   constexpr int W = WsVec<T>::kW, U = WsVec<T>::kU;
@@ -401,17 +466,23 @@ __global__ __launch_bounds__(kWsThreads, 4) void k_sketch_ws(int64_t m, int64_t 
       if (prev < m) {  // transform row prev (buffer (it - 1) & 1), write it, clear the buffer
         double2 *z = ((it - 1) & 1) ? lds2 + NP : lds2;
         const int ln = tx & 63;
-        fft_wave(z, N, tf, ln);
         double *yrow = Y + prev * ldy;
-        for (int q0 = 0; q0 < l; q0 += 256) {  // four coordinates per lane: all loads first
-          int2 cd[4];
+        if (hadamard) {  // in place on the bucket sums, natural order
+          double *zr = reinterpret_cast<double *>(z);
+          fwht_wave(zr, log2N + 1, ln);
+          for (int q = ln; q < l; q += 64) yrow[q] = zr[wpad(sel[q])] * rs;
+        } else {
+          fft_wave(z, N, tf, ln);
+          for (int q0 = 0; q0 < l; q0 += 256) {  // four coordinates per lane: all loads first
+            int2 cd[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) cd[u] = code_s[min(q0 + ln + 64 * u, l - 1)];
+            for (int u = 0; u < 4; ++u) cd[u] = code_s[min(q0 + ln + 64 * u, l - 1)];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int q = q0 + ln + 64 * u;
-            const double v = coord_value(z, cd[u], tp, rs, r2s);
-            if (q < l) yrow[q] = v;
+            for (int u = 0; u < 4; ++u) {
+              const int q = q0 + ln + 64 * u;
+              const double v = coord_value(z, cd[u], tp, rs, r2s);
+              if (q < l) yrow[q] = v;
+            }
           }
         }
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -430,12 +501,12 @@ static size_t sketch_ws_lds_bytes(int s, int l) {
 template <typename T>
 static void launch_pf(int pf, dim3 grid, size_t lds, hipStream_t st, int64_t m, int64_t n, const T *A,
                       int64_t lda, int s, int log2N, int l, const uint32_t *code, const int32_t *sel,
-                      const double2 *twf, const double2 *twp, double *Y, int64_t ldy) {
+                      const double2 *twf, const double2 *twp, double *Y, int64_t ldy, int hadamard) {
   switch (pf) {
 #define RLU_PF(P)                                                                                           \
   case P:                                                                                                   \
     hipLaunchKernelGGL((k_sketch_dense<T, P>), grid, dim3(kSketchThreads), lds, st, m, n, A, lda, s, log2N, \
-                       l, code, sel, twf, twp, Y, ldy);                                                     \
+                       l, code, sel, twf, twp, Y, ldy, hadamard);                                           \
     break;
     RLU_PF(4) RLU_PF(8) RLU_PF(16)
 #undef RLU_PF
@@ -446,8 +517,9 @@ static void launch_pf(int pf, dim3 grid, size_t lds, hipStream_t st, int64_t m, 
 hipError_t launch_sketch_dense(int64_t m, int64_t n, const void *A, int dtype, int64_t lda, int s,
                                int l, const uint32_t *code, const int32_t *sel,
                                const double2 *twf, const double2 *twp, double *Y, int64_t ldy,
-                               uint32_t *row_counter, int num_cu, hipStream_t st) {
+                               uint32_t *row_counter, int num_cu, bool hadamard, hipStream_t st) {
   const int W = dtype == RLU_F64 ? 2 : 4;
+  const int had = hadamard ? 1 : 0;
   if (s >= 8 && s <= 2 * kWsMaxN && n % W == 0 && lda % W == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
       l <= 1024) {
     const size_t lds = sketch_ws_lds_bytes(s, l);
@@ -465,10 +537,10 @@ hipError_t launch_sketch_dense(int64_t m, int64_t n, const void *A, int dtype, i
     const int log2N = ilog2_exact(s / 2);
     if (dtype == RLU_F64)
       hipLaunchKernelGGL(k_sketch_ws<double>, dim3(grid), dim3(kWsThreads), lds, st, m, n, (const double *)A, lda, s,
-                         log2N, l, code, sel, twf, twp, Y, ldy, row_counter);
+                         log2N, l, code, sel, twf, twp, Y, ldy, row_counter, had);
     else
       hipLaunchKernelGGL(k_sketch_ws<float>, dim3(grid), dim3(kWsThreads), lds, st, m, n, (const float *)A, lda, s,
-                         log2N, l, code, sel, twf, twp, Y, ldy, row_counter);
+                         log2N, l, code, sel, twf, twp, Y, ldy, row_counter, had);
     return hipGetLastError();
   }
   const size_t lds = sketch_lds_bytes(s, l);
@@ -480,9 +552,11 @@ hipError_t launch_sketch_dense(int64_t m, int64_t n, const void *A, int dtype, i
   int pf = 4;
   while (pf < 16 && (int64_t)pf * kSketchThreads < n) pf *= 2;
   if (dtype == RLU_F64)
-    launch_pf<double>(pf, dim3(grid), lds, st, m, n, (const double *)A, lda, s, log2N, l, code, sel, twf, twp, Y, ldy);
+    launch_pf<double>(pf, dim3(grid), lds, st, m, n, (const double *)A, lda, s, log2N, l, code, sel, twf, twp, Y, ldy,
+                      had);
   else
-    launch_pf<float>(pf, dim3(grid), lds, st, m, n, (const float *)A, lda, s, log2N, l, code, sel, twf, twp, Y, ldy);
+    launch_pf<float>(pf, dim3(grid), lds, st, m, n, (const float *)A, lda, s, log2N, l, code, sel, twf, twp, Y, ldy,
+                     had);
   return hipGetLastError();
 }
 

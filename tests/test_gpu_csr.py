@@ -56,6 +56,17 @@ def test_csr_sketch_matches_oracle(m, n, l, s, seed):
     assert np.all(Y[0] == 0) and np.all(Y[5] == 0)
 
 
+@pytest.mark.parametrize("m,n,l,s,seed", [(500, 400, 20, 64, 11), (300, 5000, 100, 4096, 12), (64, 100, 2, 2, 14)])
+def test_csr_hadamard_sketch_matches_oracle(m, n, l, s, seed):
+    a = make_csr(m, n, 0.02, seed, long_rows=(3, 7), empty_rows=(0, 5))
+    Y = rlu.sketch(k=1, l=l, s=s, seed=seed, csr=(*csr_dev(a.indptr, a.indices, a.data), m, n),
+                   flags=rlu.RLU_FLAG_HADAMARD).cpu().numpy()
+    ref = R.sketch_y(None, R.Params(1, l, s, seed, "hadamard"), csr=(a.indptr, a.indices, a.data, m, n))
+    assert rel_fro(Y, ref) <= 1e-10
+    assert np.abs(Y - ref).max() <= 1e-10 * np.abs(ref).max()
+    assert np.all(Y[0] == 0) and np.all(Y[5] == 0)
+
+
 @pytest.mark.parametrize("m,n,k,l,s,density", [(3000, 2000, 20, 30, 256, 0.01), (5000, 4000, 60, 70, 512, 0.005),
                                                (800, 1200, 40, 100, 1024, 0.05)])
 def test_csr_factor_matches_oracle(m, n, k, l, s, density):

@@ -78,6 +78,30 @@ def test_sketch_matches_oracle(m, n, l, s, seed, dtype):
     assert np.abs(Y - ref).max() <= 1e-10 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("m,n,l,s,seed,dtype", [
+    # wave-specialised path: every pass split of the in-place transform
+    (3000, 4096, 210, 2048, 31, np.float64),  # 11 stages: 4 4 3
+    (700, 1000, 60, 1024, 32, np.float64),    # 4 4 2
+    (260, 514, 40, 512, 33, np.float64),      # 4 4 1
+    (90, 3074, 30, 256, 34, np.float64),      # 4 4
+    (50, 64, 12, 16, 35, np.float64),         # 4
+    (50, 40, 6, 8, 36, np.float64),           # 3
+    (500, 2048, 100, 2048, 37, np.float32),   # FP32 storage
+    # one block per row (other shapes)
+    (200, 8192, 100, 8192, 38, np.float64),   # 13 stages: 4 4 4 1
+    (300, 2049, 64, 4096, 39, np.float64),    # ragged row length
+    (64, 300, 2, 2, 40, np.float64),          # s = 2
+    (64, 300, 3, 4, 41, np.float64),          # s = 4
+    (200, 777, 40, 128, 42, np.float32),
+])
+def test_hadamard_sketch_matches_oracle(m, n, l, s, seed, dtype):
+    a = np.random.default_rng(seed).standard_normal((m, n)).astype(dtype)
+    Y = rlu.sketch(to_dev(a), k=1, l=l, s=s, seed=seed, flags=rlu.RLU_FLAG_HADAMARD).cpu().numpy()
+    ref = R.sketch_y(a.astype(np.float64), R.Params(1, l, s, seed, "hadamard"))
+    assert rel_fro(Y, ref) <= 1e-10
+    assert np.abs(Y - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
 def test_sketch_respects_leading_dimension():
     a = np.random.default_rng(3).standard_normal((50, 300))
     big = torch.zeros(50, 320, dtype=torch.float64, device=DEV)
@@ -246,6 +270,19 @@ def test_stage_times_all_or_contraction_only():
     assert all(v == 0 for k, v in only.items() if k != "contract"), only
     assert ctx.stage_times() == ({k: 0.0 for k in full}, 0)    # cleared by the read
     ctx.close()
+
+
+@pytest.mark.parametrize("m,n,k,l,s", [(800, 600, 40, 48, 128), (3072, 1280, 100, 210, 512)])
+def test_factor_hadamard_matches_oracle(m, n, k, l, s):
+    A = np.random.default_rng(m + 7 * n).standard_normal((m, n))
+    for sd in range(11, 31):
+        o = R.rlu(A, R.Params(k, l, s, sd, "hadamard"))
+        if screened(o):
+            break
+    else:
+        raise RuntimeError("no screened seed")
+    g = rlu.factor(to_dev(A), k=k, l=l, s=s, seed=sd, keep_intermediates=True, flags=rlu.RLU_FLAG_HADAMARD)
+    compare_factors(A, g, o)
 
 
 @pytest.mark.parametrize("m,n,l,s", [(16, 16, 16, 16), (900, 35, 35, 64)])
