@@ -16,6 +16,8 @@ Unless --no-extras, the line also carries
            (k = 500, l = 520, s = 4096) decomposed with the contraction in
            FP64, FP32 and BF16 + one refinement step, side by side, each with
            its relative residual ||LU - PAQ||_F / ||A||_F;
+  `transforms`: the headline matrix sketched with the real Fourier and with
+           the Walsh-Hadamard transform (time, sketch rate, residual);
   `csr`:   the 200000 x 100000 CSR matrix at 0.1% density with a rank-50
            plant (k = 100, l = 110, s = 4096);
   `serving`: the request mix through the continuous-batching loop: m
@@ -88,7 +90,7 @@ def input_bytes(A):
     return A.numel() * A.element_size()
 
 
-def run(rlu, A, w, precision, steps, warmup, ctx):
+def run(rlu, A, w, precision, steps, warmup, ctx, flags=0):
     """Warm-up, then `steps` timed decompositions; returns timings and the output.
     The bench owns the device, so the calls say so (RLU_FLAG_EXCLUSIVE: the LU
     panels are ordinary launches instead of cooperative ones)."""
@@ -97,23 +99,24 @@ def run(rlu, A, w, precision, steps, warmup, ctx):
     if isinstance(A, tuple):
         kw["csr"] = A
         A = None
-    out = rlu.factor(A, flags=rlu.RLU_FLAG_EXCLUSIVE, **kw)     # allocates outputs, checks status
+    base = flags | rlu.RLU_FLAG_EXCLUSIVE
+    out = rlu.factor(A, flags=base, **kw)                       # allocates outputs, checks status
     for _ in range(warmup):
-        rlu.factor(A, out=out, check=False, flags=rlu.RLU_FLAG_EXCLUSIVE, **kw)
+        rlu.factor(A, out=out, check=False, flags=base, **kw)
     torch.cuda.synchronize()
     ctx.stage_times()                                           # clear
     # timed: HIP events around the contraction only (the roofline's kernel);
     # events at every stage boundary would idle the device a few us each
     t0 = time.perf_counter()
     for _ in range(steps):
-        rlu.factor(A, out=out, check=False, flags=rlu.RLU_FLAG_TIMING_CONTRACT | rlu.RLU_FLAG_EXCLUSIVE, **kw)
+        rlu.factor(A, out=out, check=False, flags=rlu.RLU_FLAG_TIMING_CONTRACT | base, **kw)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stages, calls = ctx.stage_times()
     contract = stages["contract"] / max(calls, 1)
     # the stage breakdown, from the same number of calls after the timed region
     for _ in range(steps):
-        rlu.factor(A, out=out, check=False, flags=rlu.RLU_FLAG_TIMING | rlu.RLU_FLAG_EXCLUSIVE, **kw)
+        rlu.factor(A, out=out, check=False, flags=rlu.RLU_FLAG_TIMING | base, **kw)
     torch.cuda.synchronize()
     stages, calls = ctx.stage_times()
     info = out.info_dict()
@@ -211,6 +214,22 @@ def forms_block(rlu, ctx, dev):
     res["sketch"] = sketch_rate(A, w, per)
     del A
     torch.cuda.empty_cache()
+    return res
+
+
+def transforms_block(rlu, A, w, ctx, ms_fourier, per_fourier, out_fourier):
+    """The headline matrix with the sketch's transform as the Walsh-Hadamard
+    matrix (RLU_FLAG_HADAMARD) beside the real Fourier one: time, sketch rate,
+    relative residual."""
+    import torch
+    res = {"fourier": {"ms_per_step": round(ms_fourier, 4), "decomps_per_s": round(1e3 / ms_fourier, 3),
+                       "sketch": sketch_rate(A, w, per_fourier), "rel_residual": rel_residual(A, out_fourier)}}
+    ms, per, out = run(rlu, A, w, "f64", steps=20, warmup=3, ctx=ctx, flags=rlu.RLU_FLAG_HADAMARD)
+    res["hadamard"] = {"ms_per_step": round(ms, 4), "decomps_per_s": round(1e3 / ms, 3),
+                       "sketch": sketch_rate(A, w, per), "rel_residual": rel_residual(A, out)}
+    del out
+    torch.cuda.empty_cache()
+    print(f"# transforms: fourier {ms_fourier:.3f} ms, hadamard {ms:.3f} ms/step", file=sys.stderr, flush=True)
     return res
 
 
@@ -371,6 +390,8 @@ def main():
     }
     if ct is not None:
         line["contract"] = ct
+    if not args.no_extras and not is_csr and precision == "f64":
+        line["transforms"] = transforms_block(rlu, A, w, ctx, ms_step, per, out)
     del out
     if not args.no_cpu_baseline and not is_csr:
         line["cpu_baseline"] = cpu_baseline(A, w)

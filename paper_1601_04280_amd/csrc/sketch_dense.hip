@@ -57,17 +57,19 @@ __device__ inline void fwht_group(double *z, int base, int stride, int ns, Idx i
     if (k < (1 << ns)) z[idx(base + k * stride)] = v[k];
 }
 
-// by one wave over a row buffer of the wave-specialised sketch (value b at
-// b + 2 (b >> 5)); the wave's LDS operations complete in order, so a pass
+// by one wave over a row buffer of the wave-specialised sketch, value b at
+// b + (b >> 4) in this form: the first pass's lanes read 17 doubles apart,
+// about two-way LDS bank conflicts (the FFT's layout, b + 2 (b >> 5), puts
+// them 16 apart); the wave's LDS operations complete in order, so a pass
 // reads what the previous one wrote
-__device__ inline int wpad(int b) { return b + 2 * (b >> 5); }
+__device__ inline int hpad(int b) { return b + (b >> 4); }
 __device__ inline void fwht_wave(double *z, int log2s, int ln) {
   const int s = 1 << log2s;
   for (int st0 = 0; st0 < log2s; st0 += 4) {
     const int ns = min(4, log2s - st0);
     for (int gi = ln; gi < (s >> ns); gi += 64) {
       const int base = ((gi >> st0) << (st0 + ns)) + (gi & ((1 << st0) - 1));
-      fwht_group(z, base, 1 << st0, ns, [](int b) { return wpad(b); });
+      fwht_group(z, base, 1 << st0, ns, [](int b) { return hpad(b); });
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   }
@@ -368,7 +370,8 @@ __global__ __launch_bounds__(kWsThreads, 4) void k_sketch_ws(int64_t m, int64_t 
     tab[nlo + i] = twf[i << tb];
     tab[2 * nlo + nhi + i] = twp[i << tb];
   }
-  for (int q = tid; q < l; q += kWsThreads) code_s[q] = coord_code(sel[q], s);
+  // per coordinate: its read-out code (the Hadamard form reads position sel[q])
+  for (int q = tid; q < l; q += kWsThreads) code_s[q] = hadamard ? make_int2(sel[q], 0) : coord_code(sel[q], s);
   const TwSplit tf{tab, tab + nlo, tb, nlo - 1};
   const TwSplit tp{tab + nlo + nhi, tab + 2 * nlo + nhi, tb, nlo - 1};
   // Rows: the block's first K rows strided by the grid (K G <= 3m/4), then
@@ -419,7 +422,7 @@ __global__ __launch_bounds__(kWsThreads, 4) void k_sketch_ws(int64_t m, int64_t 
 #pragma unroll
         for (int q = 0; q < W; ++q) {
           const uint32_t b = code_bucket(c[u][q]);
-          atomicAdd(&y0[b + 2 * (b >> 5)], code_apply(c[u][q], (double)v[u][q]));
+          atomicAdd(&y0[hadamard ? b + (b >> 4) : b + 2 * (b >> 5)], code_apply(c[u][q], (double)v[u][q]));
         }
       }
     }
@@ -470,7 +473,7 @@ __global__ __launch_bounds__(kWsThreads, 4) void k_sketch_ws(int64_t m, int64_t 
         if (hadamard) {  // in place on the bucket sums, natural order
           double *zr = reinterpret_cast<double *>(z);
           fwht_wave(zr, log2N + 1, ln);
-          for (int q = ln; q < l; q += 64) yrow[q] = zr[wpad(sel[q])] * rs;
+          for (int q = ln; q < l; q += 64) yrow[q] = zr[hpad(code_s[q].x)] * rs;
         } else {
           fft_wave(z, N, tf, ln);
           for (int q0 = 0; q0 < l; q0 += 256) {  // four coordinates per lane: all loads first
