@@ -7,7 +7,8 @@ implement the same published definitions independently.
 
 It follows Algorithm 1 (Section 3) of Aizenbud, Shabat & Averbuch,
 "Randomized LU decomposition using sparse projections", with the exact
-least-squares product of Corollary 3.2 in place of the second projection:
+least-squares product of Corollary 3.2 by default, or the paper's second
+projection Omega_2 (steps 4-5) when asked for:
 
 1. parameters of the SEM (Section 2.2) and of the SRFT (Section 2.1) from a
    seed, by a counter-based generator (``rng``);
@@ -15,7 +16,8 @@ least-squares product of Corollary 3.2 in place of the second projection:
 3. Y  = Y0 diag(d) T R, the FFT transform with sub-sampling
    (``sketch.fjl_apply``);
 4. P Y = L_y U_y, LU with partial (row) pivoting (``lu.gepp``);
-5. B  = L_y^+ P A via Householder QR (``lstsq.lstsq_product``);
+5. B  = L_y^+ P A via Householder QR (``lstsq.lstsq_product``), or
+   B = (Omega_2 L_y)^+ Omega_2 P A (``lstsq.sketched_lstsq_product``);
 6. B Q = L~ U, LU with column pivoting (``lu.colpiv_lu``);
 7. L  = L_y L~ (``rlu.rlu``).
 

@@ -1,4 +1,5 @@
-"""Algorithm 1 (Section 3) end to end, with the exact least-squares product.
+"""Algorithm 1 (Section 3) end to end: with the exact least-squares product
+(k2 = 0), or with the second projection Omega_2 of steps 4-5 (k2 > 0).
 
 Outputs follow the problem statement of Section 1 and the output line of
 Algorithm 1: permutations P (rows) and Q (columns), L (m x l, unit lower
@@ -25,6 +26,8 @@ class Params:
     s: int
     seed: int
     transform: str = "fourier"   # or "hadamard": the FJL's T (see sketch.py)
+    k2: int = 0                  # rows of Omega_2 (0: exact least-squares product)
+    l2: int = 0                  # SEM width of Omega_2 (a power of two, k2 <= l2)
 
 
 @dataclass
@@ -57,6 +60,14 @@ def check_params(m: int, n: int, p: Params):
         raise ValueError("s must be a power of two in [2, 65536]")
     if p.l > p.s:
         raise ValueError("need l <= s")
+    if p.k2 or p.l2:
+        # Algorithm 1's input line orders k_1 < l_1 < k_2 < l_2; only what the
+        # least-squares step needs (Omega_2 L_y of full column rank possible)
+        # and a power-of-two transform are required here.
+        if not (p.l <= p.k2 <= p.l2):
+            raise ValueError("need l <= k2 <= l2")
+        if p.l2 < 2 or p.l2 & (p.l2 - 1) or p.l2 > 65536:
+            raise ValueError("l2 must be a power of two in [2, 65536]")
 
 
 def sketch_params(n: int, p: Params):
@@ -64,6 +75,14 @@ def sketch_params(n: int, p: Params):
     d = rng.srft_signs(p.seed, p.s)
     sel = rng.srft_select(p.seed, p.s, p.l)
     return h, sgn, d, sel
+
+
+def omega2_params(m: int, p: Params):
+    """Random parameters of Omega_2 (Algorithm 1 step 4), streams 4-6."""
+    h2, sgn2 = rng.sem_hash(p.seed, m, p.l2, stream=rng.STREAM_SEM2)
+    d2 = rng.srft_signs(p.seed, p.l2, stream=rng.STREAM_SIGNS2)
+    sel2 = rng.srft_select(p.seed, p.l2, p.k2, stream=rng.STREAM_SELECT2)
+    return h2, sgn2, d2, sel2
 
 
 def sketch_y(A, p: Params, csr=None):
@@ -80,7 +99,8 @@ def sketch_y(A, p: Params, csr=None):
 
 
 def rlu(A, p: Params, csr=None) -> Result:
-    """Algorithm 1 with B = L_y^+ P A exactly (Corollary 3.2's product).
+    """Algorithm 1 with B = L_y^+ P A exactly (Corollary 3.2's product) when
+    p.k2 == 0, else with B = (Omega_2 L_y)^+ Omega_2 P A (steps 4-5).
 
     ``A`` is a dense array, or None with ``csr = (row_ptr, col, val, m, n)``.
     """
@@ -92,13 +112,21 @@ def rlu(A, p: Params, csr=None) -> Result:
         Aop = np.asarray(A, dtype=np.float64)
     Y = sketch_y(Aop if csr is None else None, p, csr=csr)          # steps 1-2
     Ly, Uy, perm_r, ipiv_r, zy, gy = lu.gepp(Y)                   # step 3
-    Lhat = lstsq.unpermute_rows(Ly, perm_r)
-    B = lstsq.lstsq_product(Lhat, Aop)                            # steps 5-6 (exact)
+    extra = {}
+    if p.k2:                                                      # steps 4-5 (sketched)
+        if csr is not None:
+            raise ValueError("the second projection is defined here for dense A only")
+        h2, sgn2, d2, sel2 = omega2_params(Aop.shape[0], p)
+        B, M, Z = lstsq.sketched_lstsq_product(Ly, Aop[perm_r], h2, sgn2, d2, sel2, p.l2, p.transform)
+        extra = {"M": M, "Z": Z}
+    else:
+        Lhat = lstsq.unpermute_rows(Ly, perm_r)
+        B = lstsq.lstsq_product(Lhat, Aop)                        # steps 5-6 (exact)
     Lt, U, perm_c, ipiv_c, zb, gb = lu.colpiv_lu(B)               # step 6
     L = Ly @ Lt                                                   # step 7
     return Result(L=L, U=U, perm_r=perm_r, perm_c=perm_c, ipiv_r=ipiv_r,
                   ipiv_c=ipiv_c, Y=Y, Ly=Ly, Uy=Uy, B=B, Lt=Lt,
-                  zero_pivots_y=zy, zero_pivots_b=zb, min_gap_y=gy, min_gap_b=gb)
+                  zero_pivots_y=zy, zero_pivots_b=zb, min_gap_y=gy, min_gap_b=gb, extra=extra)
 
 
 def residual_fro(A, L, U, perm_r, perm_c) -> float:

@@ -8,7 +8,8 @@ independently from its published definition:
 * mix64 is the SplitMix64 output function (Steele, Lea & Flood, "Fast
   splittable pseudorandom number generators", OOPSLA 2014; variant 13 of
   Stafford's 64-bit finalizers), gamma = 0x9E3779B97F4A7C15.
-* stream key     K_t  = mix64(seed + t * gamma)   (t = 1 SEM, 2 signs d, 3 selection)
+* stream key     K_t  = mix64(seed + t * gamma)   (t = 1 SEM, 2 signs d, 3 selection
+                 of Omega_1; t = 4, 5, 6 the same three of Omega_2)
 * draw i         r_t(i) = mix64(K_t + (i + 1) * gamma)       (all mod 2^64)
 * SEM bucket     h(j)  = r_1(j) >> (64 - log2 s)   (uniform over [0, s))
 * SEM sign       sgn(j) = 1 - 2 * (r_1(j) & 1)
@@ -28,6 +29,9 @@ GAMMA = 0x9E3779B97F4A7C15
 STREAM_SEM = 1
 STREAM_SIGNS = 2
 STREAM_SELECT = 3
+STREAM_SEM2 = 4      # Omega_2 = Pi_2 S_2 of Algorithm 1 step 4: its SEM over the m rows,
+STREAM_SIGNS2 = 5    # the SRFT diagonal and
+STREAM_SELECT2 = 6   # the SRFT selection
 
 
 def mix64(z: int) -> int:
@@ -61,13 +65,13 @@ def _log2_exact(s: int) -> int:
     return s.bit_length() - 1
 
 
-def sem_hash(seed: int, n: int, s: int):
+def sem_hash(seed: int, n: int, s: int, stream: int = STREAM_SEM):
     """Bucket h(j) in [0, s) and sign sgn(j) in {+1, -1} of every column j < n.
 
     Section 2.2: S = Phi D with Phi_{h(j), j} = 1 and D = diag(sgn).
     """
     b = _log2_exact(s)
-    key = stream_key(seed, STREAM_SEM)
+    key = stream_key(seed, stream)
     h = np.empty(n, dtype=np.int64)
     sgn = np.empty(n, dtype=np.int64)
     for j in range(n):
@@ -77,19 +81,19 @@ def sem_hash(seed: int, n: int, s: int):
     return h, sgn
 
 
-def srft_signs(seed: int, s: int) -> np.ndarray:
+def srft_signs(seed: int, s: int, stream: int = STREAM_SIGNS) -> np.ndarray:
     """Diagonal d_b in {+1, -1}, b < s (the real form of D in Section 2.1)."""
     _log2_exact(s)
-    key = stream_key(seed, STREAM_SIGNS)
+    key = stream_key(seed, stream)
     return np.array([1 - 2 * (draw(key, b) >> 63) for b in range(s)], dtype=np.int64)
 
 
-def srft_select(seed: int, s: int, l: int) -> np.ndarray:
+def srft_select(seed: int, s: int, l: int, stream: int = STREAM_SELECT) -> np.ndarray:
     """l distinct coordinates of [0, s) in draw order (the matrix S of Section 2.1)."""
     _log2_exact(s)
     if not 1 <= l <= s:
         raise ValueError("need 1 <= l <= s")
-    key = stream_key(seed, STREAM_SELECT)
+    key = stream_key(seed, stream)
     idx = list(range(s))
     sel = np.empty(l, dtype=np.int64)
     for i in range(l):
