@@ -14,7 +14,10 @@
  *   2. Y = A S^T diag(d) T R  (m x l), one streaming pass over A;
  *   3. P Y = L_y U_y, LU with partial (row) pivoting;
  *   4. B = L_y^+ P A, the exact least-squares product bounded by
- *      Corollary 3.2 (this replaces the second projection of steps 4-6);
+ *      Corollary 3.2 (by default), or the paper's own steps 4-5 when
+ *      rlu_params.k2 > 0: a second projection Omega_2 = Pi_2 S_2 (k2 x m,
+ *      built like the first over the m rows of P A, with SEM width l2) and
+ *      B = (Omega_2 L_y)^+ Omega_2 P A through the normal equations;
  *   5. B Q = L~ U, LU with column ("right partial") pivoting;
  *   6. L = L_y L~.
  *
@@ -32,6 +35,8 @@
  *     SplitMix64 output function (Steele, Lea & Flood 2014), gamma =
  *     0x9E3779B97F4A7C15, stream key K_t = mix64(seed + t*gamma) for t = 1
  *     (SEM), 2 (d), 3 (selection), draw r_t(i) = mix64(K_t + (i+1)*gamma);
+ *     Omega_2 uses t = 4, 5, 6 for the same three, with l2 and k2 in place
+ *     of s and l and the pivoted row position i in place of the column j;
  *     h(j) = r_1(j) >> (64 - log2 s), sgn(j) = 1 - 2*(r_1(j) & 1),
  *     d_b = 1 - 2*(r_2(b) >> 63), sel by a partial Fisher-Yates shuffle of
  *     [0, s) with j = i + mulhi64(r_3(i), s - i).
@@ -107,6 +112,11 @@ typedef struct {
   int32_t precision;        /* rlu_precision                                        */
   uint64_t seed;            /* seed of the random parameters                        */
   uint32_t flags;           /* RLU_FLAG_* bits                                      */
+  int32_t k2;               /* rows of the second projection Omega_2 of Algorithm 1
+                             * steps 4-5; 0 (with l2 = 0): B is the exact product
+                             * L_y^+ P A of Corollary 3.2.  Else l <= k2 <= l2,
+                             * k2 <= 1024, dense A, RLU_PREC_F64 only           */
+  int32_t l2;               /* SEM width of Omega_2: a power of two in [2, 8192]   */
   uint32_t reserved;        /* must be 0                                            */
 } rlu_params;
 
@@ -139,10 +149,14 @@ enum {
   RLU_STAGE_PARAMS = 0,      /* random parameters (step 1)                        */
   RLU_STAGE_SKETCH = 1,      /* Y = A Omega^T (step 2)                            */
   RLU_STAGE_LU_Y = 2,        /* row-pivoted LU of Y (step 3)                      */
-  RLU_STAGE_CONTRACT = 3,    /* W = Lhat^T A (step 4, the dominant product)       */
-  RLU_STAGE_GRAM = 4,        /* G = Lhat^T Lhat                                    */
-  RLU_STAGE_CHOL = 5,        /* inverse Cholesky factor of G and G^{-1}            */
-  RLU_STAGE_SOLVE = 6,       /* B^T = W^T G^{-1} (or the refined reduced form)     */
+  RLU_STAGE_CONTRACT = 3,    /* W = Lhat^T A (step 4, the dominant product); with
+                              * k2 > 0, Z = Omega_2 P A instead                   */
+  RLU_STAGE_GRAM = 4,        /* G = Lhat^T Lhat; with k2 > 0, M = Omega_2 L_y and
+                              * G = M^T M                                         */
+  RLU_STAGE_CHOL = 5,        /* inverse Cholesky factor of G and G^{-1} (k2 > 0:
+                              * and M G^{-1})                                     */
+  RLU_STAGE_SOLVE = 6,       /* B^T = W^T G^{-1} (or the refined reduced form;
+                              * k2 > 0: B^T = Z^T M G^{-1})                       */
   RLU_STAGE_LU_B = 7,        /* column-pivoted LU of B (step 5)                   */
   RLU_STAGE_ASSEMBLE = 8,    /* L~, U and L = L_y L~ (step 6)                     */
   RLU_NUM_STAGES = 9
@@ -169,7 +183,8 @@ typedef struct {
   int32_t *ipiv_c;          /* optional (NULL): l column exchanges of step 5        */
   double *Y;  int64_t ldy;  /* optional (NULL): the sketch Y, m x l                 */
   double *Uy;               /* optional (NULL): U_y, l x l, leading dimension l     */
-  double *B;                /* optional (NULL): B = L_y^+ P A, l x n, ld n          */
+  double *B;                /* optional (NULL): B = L_y^+ P A (k2 > 0: the sketched
+                             * product of steps 4-5), l x n, ld n                  */
   rlu_info *info;           /* required: device record, see rlu_info                */
 } rlu_factors;
 

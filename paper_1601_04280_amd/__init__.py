@@ -56,7 +56,7 @@ class Matrix(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("l", ctypes.c_int32), ("s", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("k2", ctypes.c_int32), ("l2", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
 
 
 class Info(ctypes.Structure):
@@ -185,9 +185,9 @@ def default_context(device: int = 0) -> Context:
     return _default_ctx[device]
 
 
-def _params(k, l, s, seed, precision="f64", flags=0) -> Params:
+def _params(k, l, s, seed, precision="f64", flags=0, k2=0, l2=0) -> Params:
     return Params(int(k), int(l), int(s), PRECISIONS[precision], int(seed) & ((1 << 64) - 1),
-                  int(flags), 0)
+                  int(flags), int(k2), int(l2), 0)
 
 
 def _dense_matrix(A) -> Matrix:
@@ -265,11 +265,12 @@ class Factorization:
                 "timeouts": v[4], "bad_index": v[5]}
 
 
-def workspace_size(A=None, *, k: int, l: int, s: int, precision: str = "f64", csr=None, ctx: Context = None) -> int:
+def workspace_size(A=None, *, k: int, l: int, s: int, precision: str = "f64", csr=None, ctx: Context = None,
+                   k2: int = 0, l2: int = 0) -> int:
     """Bytes of workspace one decomposition of this problem needs."""
     ctx = ctx or default_context()
     mat = _dense_matrix(A) if csr is None else _csr_matrix(*csr)
-    p = _params(k, l, s, 0, precision)
+    p = _params(k, l, s, 0, precision, 0, k2, l2)
     nbytes = ctypes.c_size_t()
     _check(load_library().rlu_workspace_size(ctx.handle, ctypes.byref(mat), ctypes.byref(p), ctypes.byref(nbytes)))
     return nbytes.value
@@ -298,13 +299,16 @@ def _factors(out: Factorization) -> Factors:
 
 def factor(A=None, *, k: int, l: int, s: int, seed: int, precision: str = "f64", csr=None,
            ctx: Context = None, keep_intermediates: bool = False, check: bool = True, flags: int = 0,
-           out: Factorization = None) -> Factorization:
-    """PAQ ~ LU on the device.  ``check`` synchronises and raises on a device-side error."""
+           out: Factorization = None, k2: int = 0, l2: int = 0) -> Factorization:
+    """PAQ ~ LU on the device.  ``check`` synchronises and raises on a device-side error.
+
+    ``k2 > 0`` computes B through the second projection Omega_2 (k2 x m, SEM
+    width ``l2``) of Algorithm 1 steps 4-5 instead of the exact product."""
     torch = _torch()
     ctx = ctx or default_context()
     mat = _dense_matrix(A) if csr is None else _csr_matrix(*csr)
     m, n = mat.m, mat.n
-    p = _params(k, l, s, seed, precision, flags)
+    p = _params(k, l, s, seed, precision, flags, k2, l2)
     lib = load_library()
     nbytes = ctypes.c_size_t()
     _check(lib.rlu_workspace_size(ctx.handle, ctypes.byref(mat), ctypes.byref(p), ctypes.byref(nbytes)))
@@ -337,10 +341,11 @@ class Server:
         self._running = True
 
     def submit(self, A=None, *, k: int, l: int, s: int, seed: int, precision: str = "f64", csr=None,
-               out: Factorization = None, keep_intermediates: bool = False, sync_inputs: bool = True) -> int:
+               out: Factorization = None, keep_intermediates: bool = False, sync_inputs: bool = True,
+               k2: int = 0, l2: int = 0) -> int:
         torch = _torch()
         mat = _dense_matrix(A) if csr is None else _csr_matrix(*csr)
-        p = _params(k, l, s, seed, precision)
+        p = _params(k, l, s, seed, precision, 0, k2, l2)
         if out is None:
             out = alloc_factors(mat.m, mat.n, l, self.ctx.device, keep_intermediates)
         if sync_inputs:

@@ -30,6 +30,7 @@ rlu_status hip_fail(hipError_t e, const char *what) {
 void sketch_dense_set_attrs();
 void sketch_csr_set_attrs();
 
+constexpr int kMaxK2 = 1024;  // rows of Omega_2: the transform kernel's output limit
 constexpr int kMaxL = 544;  // l x 34 doubles of the Cholesky panel must fit in LDS
 
 // ---------------------------------------------------------------------------
@@ -71,6 +72,17 @@ rlu_status validate_params(const rlu_matrix *A, const rlu_params *p) {
   if (p->precision < RLU_PREC_F64 || p->precision > RLU_PREC_BF16_REFINED) return fail(RLU_ERR_INVALID_ARG, "unknown precision %d", p->precision);
   if (p->flags & ~(RLU_FLAG_VALIDATE | RLU_FLAG_TIMING | RLU_FLAG_EXCLUSIVE | RLU_FLAG_TIMING_CONTRACT |
                    RLU_FLAG_HADAMARD)) return fail(RLU_ERR_INVALID_ARG, "unknown flag bits 0x%x", p->flags);
+  if (p->k2 != 0 || p->l2 != 0) {  // the second projection of steps 4-5
+    if (p->l2 < 2 || p->l2 > kMaxS || !is_pow2(p->l2))
+      return fail(RLU_ERR_INVALID_ARG, "l2 (%d) must be a power of two in [2, %d]", p->l2, kMaxS);
+    if (p->k2 < p->l || p->k2 > p->l2 || p->k2 > kMaxK2)
+      return fail(RLU_ERR_INVALID_ARG, "need l <= k2 <= min(l2, %d) (l=%d k2=%d l2=%d)", kMaxK2, p->l, p->k2, p->l2);
+    if (p->precision != RLU_PREC_F64)
+      return fail(RLU_ERR_INVALID_ARG, "the second projection is built for RLU_PREC_F64 only");
+    if (A && A->layout != RLU_DENSE_ROW_MAJOR)
+      return fail(RLU_ERR_INVALID_ARG, "the second projection is built for dense A only");
+    if (A && A->m > INT32_MAX) return fail(RLU_ERR_INVALID_ARG, "the second projection needs m < 2^31");
+  }
   return RLU_OK;
 }
 
@@ -118,10 +130,14 @@ rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_pa
   if (!plan_gepp(A->n, p->l, cx.caps, &fp->pb, &why)) return fail(RLU_ERR_INVALID_ARG, "column-pivoted LU: %s", why.c_str());
   const int64_t m = A->m, n = A->n;
   const int l = p->l;
-  fp->splits_w = choose_splits(n, l, m, cx.caps.num_cu);
-  fp->splits_g = choose_splits(l, l, m, cx.caps.num_cu);
+  fp->k2 = p->k2;
+  fp->l2 = p->l2;
+  const bool second = p->k2 > 0;
+  const int64_t kc = second ? p->k2 : m;  // depth of the contraction and of the Gram matrix
+  fp->splits_w = second ? 1 : choose_splits(n, l, kc, cx.caps.num_cu);
+  fp->splits_g = choose_splits(l, l, kc, cx.caps.num_cu);
   fp->splits_i = choose_splits(l, l, l, cx.caps.num_cu);
-  fp->splits_b = choose_splits(n, l, l, cx.caps.num_cu);
+  fp->splits_b = choose_splits(n, l, second ? kc : l, cx.caps.num_cu);
   Carver cv;
   plan_sketch_part(cv, *fp, n, l, p->s);
   fp->sketch_total = cv.off;
@@ -148,6 +164,20 @@ rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_pa
       !plan_precision(m, n, l, p->precision, cx.caps.num_cu, &fp->pp))
     return fail(RLU_ERR_INVALID_ARG, "unknown precision %d", p->precision);
   fp->prec = cv.take(fp->pp.total);
+  const size_t k2 = second ? (size_t)p->k2 : 0, l2 = second ? (size_t)p->l2 : 0;
+  fp->o2start = cv.take(second ? (l2 + 1) * 4 : 0);
+  fp->o2list = cv.take(second ? (size_t)m * 4 : 0);
+  fp->o2code = cv.take(l2 * 4);
+  fp->o2sel = cv.take(k2 * 4);
+  fp->o2twf = cv.take(second ? std::max<size_t>(1, l2 / 2) * 16 : 0);
+  fp->o2twp = cv.take(second ? std::max<size_t>(1, l2 / 2) * 16 : 0);
+  fp->Z0T = cv.take((size_t)n * l2 * 8);
+  fp->ZT = cv.take((size_t)n * k2 * 8);
+  fp->Zs = cv.take(k2 * (size_t)n * 8);
+  fp->M0T = cv.take((size_t)l * l2 * 8);
+  fp->MT = cv.take((size_t)l * k2 * 8);
+  fp->Ms = cv.take(k2 * l * 8);
+  fp->Nm = cv.take(k2 * l * 8);
   fp->total = cv.off;
   return RLU_OK;
 }
@@ -162,6 +192,13 @@ static rlu_status run_params(const FactorPlan &fp, const rlu_params *p, void *ws
   launch_sem_codes(fp.n, p->s, p->seed, at<uint32_t>(ws, fp.code), nullptr, nullptr, st);
   launch_srft_params(p->s, p->l, p->seed, nullptr, at<int32_t>(ws, fp.sel), at<double2>(ws, fp.twf),
                      at<double2>(ws, fp.twp), st);
+  if (fp.k2 > 0) {  // Omega_2 (step 4): data-independent, drawn with Omega_1
+    hipError_t e2 = launch_omega2_lists(fp.m, fp.l2, p->seed, at<int32_t>(ws, fp.o2start), at<uint32_t>(ws, fp.o2list),
+                                        at<uint32_t>(ws, fp.o2code), st);
+    if (e2 != hipSuccess) return hip_fail(e2, "second projection lists");
+    launch_srft_params(fp.l2, fp.k2, p->seed, nullptr, at<int32_t>(ws, fp.o2sel), at<double2>(ws, fp.o2twf),
+                       at<double2>(ws, fp.o2twp), st, true);
+  }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? RLU_OK : hip_fail(e, "parameter kernels");
 }
@@ -186,6 +223,25 @@ static rlu_status run_sketch(const rlu_ctx_impl &cx, const FactorPlan &fp, const
                           cx.caps.num_cu, (p->flags & RLU_FLAG_HADAMARD) != 0, st);
   }
   return e == hipSuccess ? RLU_OK : hip_fail(e, "sketch kernel");
+}
+
+// Omega_2 X for X with m rows (ncols columns), Algorithm 1 steps 4-5:
+// (S_2 P X)^T into Z0T, the transform down its columns as the row sketch of
+// Z0T (identity SEM, d_2 in the codes) into ZT, then Zs = Omega_2 P X
+// (k2 x ncols, ld ncols).
+static rlu_status omega2_apply(const rlu_ctx_impl &cx, const FactorPlan &fp, const void *X, int dtype, int64_t ldx,
+                               int64_t ncols, const int32_t *perm, double *Z0T, double *ZT, double *Zs,
+                               uint32_t *row_counter, bool hadamard, void *ws, hipStream_t st) {
+  hipError_t e = launch_omega2_gather(ncols, X, dtype, ldx, perm, at<int32_t>(ws, fp.o2start),
+                                      at<uint32_t>(ws, fp.o2list), fp.l2, Z0T, fp.l2, st);
+  if (e != hipSuccess) return hip_fail(e, "second projection: sparse embedding");
+  e = launch_sketch_dense(ncols, fp.l2, Z0T, RLU_F64, fp.l2, fp.l2, fp.k2, at<uint32_t>(ws, fp.o2code),
+                          at<int32_t>(ws, fp.o2sel), at<double2>(ws, fp.o2twf), at<double2>(ws, fp.o2twp), ZT, fp.k2,
+                          row_counter, cx.caps.num_cu, hadamard, st);
+  if (e != hipSuccess) return hip_fail(e, "second projection: transform");
+  if ((e = launch_transpose(ncols, fp.k2, ZT, fp.k2, Zs, ncols, st)) != hipSuccess)
+    return hip_fail(e, "second projection: transpose");
+  return RLU_OK;
 }
 
 // Start / end events of the recorded stages of one timed call (no-ops when
@@ -298,18 +354,26 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   // to run in several rounds of blocks, the G chain runs on the auxiliary
   // stream beside it; a one-round contraction holds every CU and would only
   // delay the chain (and one of its own blocks), so then the chain runs first.
-  const bool overlap = A->layout == RLU_CSR || (double)m * (double)n * (double)l >= 1e11;
+  const bool second = fp.k2 > 0;
+  const bool hadamard = (p->flags & RLU_FLAG_HADAMARD) != 0;
+  const bool overlap = second || A->layout == RLU_CSR || (double)m * (double)n * (double)l >= 1e11;
   hipStream_t gs = overlap ? ax.aux : st;
   if (overlap) {
     if ((e = hipEventRecord(ax.fork, st)) != hipSuccess || (e = hipStreamWaitEvent(ax.aux, ax.fork, 0)) != hipSuccess)
       return hip_fail(e, "fork");
   }
   sm.begin(RLU_STAGE_GRAM, gs);
+  double *Ms = at<double>(ws, fp.Ms);
+  if (second) {  // M = Omega_2 L_y = Omega_2 P Lhat
+    rs = omega2_apply(cx, fp, Lhat, RLU_F64, l, l, out->perm_r, at<double>(ws, fp.M0T), at<double>(ws, fp.MT), Ms,
+                      ctl + 4, hadamard, ws, gs);
+    if (rs != RLU_OK) return rs;
+  }
   {
     GemmArgs g{};
-    g.M = l; g.N = l; g.K = m;
-    g.A = Lhat; g.lda = l; g.a_dtype = RLU_F64; g.trans_a = true;
-    g.B = Lhat; g.ldb = l;
+    g.M = l; g.N = l; g.K = second ? fp.k2 : m;
+    g.A = second ? Ms : Lhat; g.lda = l; g.a_dtype = RLU_F64; g.trans_a = true;
+    g.B = second ? Ms : Lhat; g.ldb = l;
     g.C = at<double>(ws, fp.Gm); g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
     e = gemm_f64_splitk(g, fp.splits_g, at<double>(ws, fp.parts_g), gs);
     if (e != hipSuccess) return hip_fail(e, "Gram matrix");
@@ -327,12 +391,24 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     if ((e = gemm_f64_splitk(g, fp.splits_i, at<double>(ws, fp.parts_g), gs)) != hipSuccess)
       return hip_fail(e, "inverse Gram");
   }
+  if (second) {  // M G^{-1} (k2 x l), so that B^T = Z^T (M G^{-1})
+    GemmArgs g{};
+    g.M = fp.k2; g.N = l; g.K = l;
+    g.A = Ms; g.lda = l; g.a_dtype = RLU_F64; g.trans_a = false;
+    g.B = at<double>(ws, fp.Ginv); g.ldb = l;
+    g.C = at<double>(ws, fp.Nm); g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
+    if ((e = gemm_f64(g, gs)) != hipSuccess) return hip_fail(e, "M G^{-1}");
+  }
   sm.end(RLU_STAGE_CHOL, gs);
   if (overlap && (e = hipEventRecord(ax.join, ax.aux)) != hipSuccess) return hip_fail(e, "join");
 
   double *Wt = at<double>(ws, fp.Wt);
   sm.begin(RLU_STAGE_CONTRACT, st);
-  if (A->layout == RLU_CSR) {
+  if (second) {  // Z = Omega_2 P A
+    rs = omega2_apply(cx, fp, A->values, A->dtype, A->ld, n, out->perm_r, at<double>(ws, fp.Z0T),
+                      at<double>(ws, fp.ZT), at<double>(ws, fp.Zs), ctl + 5, hadamard, ws, st);
+    if (rs != RLU_OK) return rs;
+  } else if (A->layout == RLU_CSR) {
     e = contraction_csr(m, n, l, A->row_ptr, A->col_idx, (const double *)A->values, A->nnz, Lhat, Wt,
                         at<void>(ws, fp.csc), cx.caps.num_cu, st);
     if (e != hipSuccess) return hip_fail(e, "sparse contraction");
@@ -355,6 +431,14 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     // one refinement step of the BF16 contraction; writes Bt
     e = precision_refine(fp.pp, A, l, Wt, at<double>(ws, fp.Ginv), at<double>(ws, fp.Bt), at<void>(ws, fp.prec), st);
     if (e != hipSuccess) return hip_fail(e, "refinement");
+  } else if (second) {  // B^T = Z^T (M G^{-1}) = ((Omega_2 L_y)^+ Omega_2 P A)^T
+    GemmArgs g{};
+    g.M = n; g.N = l; g.K = fp.k2;
+    g.A = at<double>(ws, fp.Zs); g.lda = n; g.a_dtype = RLU_F64; g.trans_a = true;
+    g.B = at<double>(ws, fp.Nm); g.ldb = l;
+    g.C = at<double>(ws, fp.Bt); g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
+    if ((e = gemm_f64_splitk(g, fp.splits_b, at<double>(ws, fp.parts), st)) != hipSuccess)
+      return hip_fail(e, "sketched least-squares product");
   } else {  // B^T = W^T G^{-1}
     GemmArgs g{};
     g.M = n; g.N = l; g.K = l;

@@ -16,6 +16,9 @@ constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
 constexpr int kStreamSem = 1;
 constexpr int kStreamSigns = 2;
 constexpr int kStreamSelect = 3;
+constexpr int kStreamSem2 = 4;     // the same three draws of Omega_2 (Algorithm 1 step 4)
+constexpr int kStreamSigns2 = 5;
+constexpr int kStreamSelect2 = 6;
 
 __host__ __device__ inline uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;

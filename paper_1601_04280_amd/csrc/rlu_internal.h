@@ -28,8 +28,19 @@ constexpr int kSketchThreads = 256;
 // ---- parameters -----------------------------------------------------------
 void launch_sem_codes(int64_t n, int s, uint64_t seed, uint32_t *code, int32_t *h, int8_t *sgn,
                       hipStream_t st);
+// second: the streams of Omega_2 (else Omega_1)
 void launch_srft_params(int s, int l, uint64_t seed, int8_t *d, int32_t *sel, double2 *twf,
-                        double2 *twp, hipStream_t st);
+                        double2 *twp, hipStream_t st, bool second = false);
+// Omega_2 (Algorithm 1 step 4): bucket lists of its SEM over m positions
+// (start: l2 + 1 offsets into list; list: position | sign bit 31) and the
+// transform step's codes (code2: l2 entries)
+hipError_t launch_omega2_lists(int64_t m, int l2, uint64_t seed, int32_t *start, uint32_t *list,
+                               uint32_t *code2, hipStream_t st);
+// Z0T (ncols x l2, ldz) = (S_2 P X)^T for X with m rows (row i of P X is
+// row perm[i] of X); dtype RLU_F64 or RLU_F32
+hipError_t launch_omega2_gather(int64_t ncols, const void *X, int dtype, int64_t ldx, const int32_t *perm,
+                                const int32_t *start, const uint32_t *list, int l2, double *Z0T, int64_t ldz,
+                                hipStream_t st);
 
 // ---- sketch -----------------------------------------------------------------
 struct SketchPlan {
@@ -179,9 +190,14 @@ struct FactorPlan {
   int splits_w, splits_g;
   int splits_i, splits_b;  // G^{-1} = L^{-T} L^{-1} (in parts_g) and B^T = W^T G^{-1} (in parts)
   PrecPlan pp;
+  int k2, l2;  // second projection (k2 > 0), else the exact product
   // offsets (bytes) into the workspace
   size_t ctl, code, sel, twf, twp, Y, slots, csc, Lhat, Uy, Wt, parts, parts_g, Gm, Linv, Dinv, Ginv, Bt,
       Lph, Up, Lt, prec;
+  // second projection: bucket lists and transform parameters of Omega_2,
+  // (S_2 P A)^T, (Omega_2 P A)^T, Z = Omega_2 P A, the same three for L_y,
+  // and M G^{-1}
+  size_t o2start, o2list, o2code, o2sel, o2twf, o2twp, Z0T, ZT, Zs, M0T, MT, Ms, Nm;
   size_t total;
   size_t sketch_total;
 };

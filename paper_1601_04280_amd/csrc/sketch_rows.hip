@@ -1,0 +1,149 @@
+// The second projection of Algorithm 1 (steps 4-5): Omega_2 = Pi_2 S_2,
+// k_2 x m, applied to P A and to L_y along their m rows.
+//
+// S_2 (an l_2 x m SEM, Section 2.2) sends row i of P A, with sign sgn_2(i),
+// into bucket h_2(i).  On the device that is a gather rather than a scatter:
+// the rows of each bucket are listed once (k_omega2_lists), and one block per
+// (64 buckets x 64 columns) tile sums the listed rows of A, in pivoted order,
+// reading every element of A exactly once, then writes its tile transposed:
+// Z0^T (cols x l_2), so that each column of S_2 P A is one contiguous row.
+// Pi_2 (the SRFT of Section 2.1 down those columns) is then the row sketch
+// kernel run on Z0^T with the identity as its SEM and d_2 folded into the
+// codes.
+#include "rlu_device.h"
+#include "rlu_internal.h"
+
+namespace rlu {
+
+constexpr int kListThreads = 1024;
+constexpr int kTile = 64;  // buckets and columns of one gather tile
+
+// Bucket lists of S_2 over the m pivoted positions: start[b] .. start[b+1]
+// index `list`, whose entries are a position i with bit 31 set when
+// sgn_2(i) = -1.  Also the codes of the transform step: code2[j] = j with
+// bit 31 set when d_2(j) = -1.  One block; counts, then offsets, then
+// placement (in any order within a bucket), all in LDS.
+__global__ void __launch_bounds__(kListThreads) k_omega2_lists(int64_t m, int l2, int log2l2, uint64_t key_sem,
+                                                               uint64_t key_signs, int32_t *__restrict__ start,
+                                                               uint32_t *__restrict__ list,
+                                                               uint32_t *__restrict__ code2) {
+  extern __shared__ uint32_t cnt[];  // l2 counters, then kListThreads / 64 wave totals
+  uint32_t *wsum = cnt + l2;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int b = tid; b < l2; b += kListThreads) {
+    cnt[b] = 0;
+    code2[b] = (uint32_t)b | ((uint32_t)(draw(key_signs, (uint64_t)b) >> 63) << 31);
+  }
+  __syncthreads();
+  for (int64_t i = tid; i < m; i += kListThreads) {
+    const uint64_t r = draw(key_sem, (uint64_t)i);
+    atomicAdd(&cnt[(uint32_t)(r >> (64 - log2l2))], 1u);
+  }
+  __syncthreads();
+  // exclusive scan of the counts: each thread a run of `per` buckets
+  const int per = (l2 + kListThreads - 1) / kListThreads;
+  const int b0 = tid * per, b1 = min(l2, b0 + per);
+  uint32_t run = 0;
+  for (int b = b0; b < b1; ++b) run += cnt[b];
+  uint32_t incl = run;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += o;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  uint32_t base = 0;
+  for (int w = 0; w < wv; ++w) base += wsum[w];
+  uint32_t off = base + incl - run;
+  __syncthreads();  // every total read before the counts turn into cursors
+  for (int b = b0; b < b1; ++b) {
+    const uint32_t c = cnt[b];
+    start[b] = (int32_t)off;
+    cnt[b] = off;
+    off += c;
+  }
+  if (tid == 0) start[l2] = (int32_t)m;
+  __syncthreads();
+  for (int64_t i = tid; i < m; i += kListThreads) {
+    const uint64_t r = draw(key_sem, (uint64_t)i);
+    const uint32_t slot = atomicAdd(&cnt[(uint32_t)(r >> (64 - log2l2))], 1u);
+    list[slot] = (uint32_t)i | ((uint32_t)(r & 1u) << 31);
+  }
+}
+
+template <typename T>
+__device__ inline double load_nt(const T *p) {
+  return (double)__builtin_nontemporal_load(p);
+}
+
+// Z0^T[c, b] = sum over the list of bucket b of sgn_2(i) X[perm[i], c]:
+// S_2 P X, transposed.  Block (bx, by): columns 64 bx .., buckets 64 by ..;
+// wave w sums buckets w, w + 4, ..., lane = column.  X is read once overall.
+template <typename T>
+__global__ void __launch_bounds__(256) k_omega2_gather(int64_t ncols, const T *__restrict__ X, int64_t ldx,
+                                                        const int32_t *__restrict__ perm,
+                                                        const int32_t *__restrict__ start,
+                                                        const uint32_t *__restrict__ list, int l2,
+                                                        double *__restrict__ Z0T, int64_t ldz) {
+  __shared__ double tile[kTile][kTile + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t c0 = (int64_t)blockIdx.x * kTile, b0 = (int64_t)blockIdx.y * kTile;
+  const int64_t col = c0 + lane;
+  const bool cok = col < ncols;
+  const T *xc = X + (cok ? col : 0);
+  for (int bb = wv; bb < kTile; bb += 4) {
+    const int64_t b = b0 + bb;
+    double acc = 0.0;
+    if (b < l2) {
+      int e = start[b];
+      const int e1 = start[b + 1];
+      for (; e + 4 <= e1; e += 4) {
+        uint32_t c[4];
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) c[u] = list[e + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = cok ? load_nt(xc + (int64_t)perm[c[u] & 0x7FFFFFFFu] * ldx) : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += (c[u] >> 31) ? -v[u] : v[u];
+      }
+      for (; e < e1; ++e) {
+        const uint32_t c = list[e];
+        const double v = cok ? load_nt(xc + (int64_t)perm[c & 0x7FFFFFFFu] * ldx) : 0.0;
+        acc += (c >> 31) ? -v : v;
+      }
+    }
+    tile[bb][lane] = acc;
+  }
+  __syncthreads();
+  const int64_t bo = b0 + lane;
+  if (bo < l2) {
+    for (int c = wv; c < kTile; c += 4)
+      if (c0 + c < ncols) Z0T[(c0 + c) * ldz + bo] = tile[lane][c];
+  }
+}
+
+hipError_t launch_omega2_lists(int64_t m, int l2, uint64_t seed, int32_t *start, uint32_t *list,
+                               uint32_t *code2, hipStream_t st) {
+  if (m < 1 || m > INT32_MAX || l2 < 2 || l2 > kMaxS || (l2 & (l2 - 1))) return hipErrorInvalidValue;
+  const size_t lds = ((size_t)l2 + kListThreads / 64) * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_omega2_lists, dim3(1), dim3(kListThreads), lds, st, m, l2, ilog2_exact(l2),
+                     stream_key(seed, kStreamSem2), stream_key(seed, kStreamSigns2), start, list, code2);
+  return hipGetLastError();
+}
+
+hipError_t launch_omega2_gather(int64_t ncols, const void *X, int dtype, int64_t ldx, const int32_t *perm,
+                                const int32_t *start, const uint32_t *list, int l2, double *Z0T, int64_t ldz,
+                                hipStream_t st) {
+  if (ncols < 1 || l2 < 1 || ldz < l2 || ldx < ncols) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)ceil_div(ncols, kTile), (unsigned)ceil_div(l2, kTile));
+  if (dtype == RLU_F64)
+    hipLaunchKernelGGL(k_omega2_gather<double>, grid, dim3(256), 0, st, ncols, (const double *)X, ldx, perm, start,
+                       list, l2, Z0T, ldz);
+  else
+    hipLaunchKernelGGL(k_omega2_gather<float>, grid, dim3(256), 0, st, ncols, (const float *)X, ldx, perm, start,
+                       list, l2, Z0T, ldz);
+  return hipGetLastError();
+}
+
+}  // namespace rlu

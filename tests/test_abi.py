@@ -52,7 +52,7 @@ int main(void) {
   printf("rlu_matrix %zu\nrlu_params %zu\nrlu_info %zu\nrlu_factors %zu\n",
          sizeof(rlu_matrix), sizeof(rlu_params), sizeof(rlu_info), sizeof(rlu_factors));
   F(rlu_matrix, values); F(rlu_matrix, ld); F(rlu_matrix, nnz);
-  F(rlu_params, seed); F(rlu_params, flags);
+  F(rlu_params, seed); F(rlu_params, flags); F(rlu_params, k2); F(rlu_params, l2);
   F(rlu_factors, perm_r); F(rlu_factors, Y); F(rlu_factors, info);
   F(rlu_info, bad_index);
   return 0;
@@ -75,6 +75,8 @@ int main(void) {
     assert int(got["rlu_factors.Y"]) == rlu.Factors.Y.offset
     assert int(got["rlu_factors.info"]) == rlu.Factors.info.offset
     assert int(got["rlu_info.bad_index"]) == rlu.Info.bad_index.offset
+    assert int(got["rlu_params.k2"]) == rlu.Params.k2.offset
+    assert int(got["rlu_params.l2"]) == rlu.Params.l2.offset
 
 
 def test_errors_are_reported_without_a_device():
@@ -85,4 +87,11 @@ def test_errors_are_reported_without_a_device():
     assert b"k <= l" in lib.rlu_last_error()
     p = rlu.Params(2, 4, 12, 0, 1, 0, 0)        # s not a power of two
     assert lib.rlu_sketch_params(ctypes.byref(p), 16, None, None, None, None, None) == rlu.RLU_ERR_INVALID_ARG
+    # second projection: l <= k2 <= l2, l2 a power of two, FP64 only
+    for k2, l2, prec in [(2, 8, 0), (16, 8, 0), (6, 12, 0), (6, 16, 1), (4, 0, 0), (0, 16, 0)]:
+        p = rlu.Params(2, 4, 8, prec, 1, 0, k2, l2, 0)
+        assert lib.rlu_sketch_params(ctypes.byref(p), 16, None, None, None, None, None) == rlu.RLU_ERR_INVALID_ARG
+    assert b"l2" in lib.rlu_last_error() or b"k2" in lib.rlu_last_error()
+    p = rlu.Params(2, 4, 8, 0, 1, 0, 6, 16, 0)   # valid (without a device the call may still fail)
+    assert lib.rlu_sketch_params(ctypes.byref(p), 16, None, None, None, None, None) != rlu.RLU_ERR_INVALID_ARG
     assert lib.rlu_create(0, None) == rlu.RLU_ERR_INVALID_ARG
