@@ -11,13 +11,17 @@ Prints one JSON line.  `value` is decompositions per second of the headline
 workload; `roofline` describes the stage whose kernels dominate the step
 among the bandwidth/MFMA-bound ones, timed with HIP events on the library's
 stream inside the timed region; `cpu_baseline` times the oracle on the host.
-Unless --no-extras, the line also carries
+Unless --no-extras (or a shorter --extras list), the line also carries
   `forms`: the 32768 x 16384 FP32-stored matrix with sigma_i = exp(-i/100)
            (k = 500, l = 520, s = 4096) decomposed with the contraction in
            FP64, FP32 and BF16 + one refinement step, side by side, each with
            its relative residual ||LU - PAQ||_F / ||A||_F;
   `transforms`: the headline matrix sketched with the real Fourier and with
            the Walsh-Hadamard transform (time, sketch rate, residual);
+  `second_projection`: the headline matrix with B from the paper's second
+           projection Omega_2 (k2 = 840, l2 = 4096 and k2 = 420, l2 = 2048)
+           in place of the exact product: time, residual against the exact
+           product's, and the rate of the Omega_2 pass over A;
   `csr`:   the 200000 x 100000 CSR matrix at 0.1% density with a rank-50
            plant (k = 100, l = 110, s = 4096);
   `serving`: the request mix through the continuous-batching loop: m
@@ -38,6 +42,7 @@ import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
+EXTRAS = ("transforms", "second_projection", "forms", "csr", "serving")
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 
 WORKLOADS = {
@@ -58,6 +63,8 @@ def parse():
     ap.add_argument("--precision", choices=["f64", "f32", "bf16"], default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default=",".join(EXTRAS),
+                    help="comma-separated blocks to add to the line (default: all of %s)" % ", ".join(EXTRAS))
     ap.add_argument("--gaussian-data", action="store_true",
                     help="N(0,1) entries of the workload's shape instead of its spectrum (for counter runs: "
                          "the kernels' memory traffic does not depend on the values, and the profiler "
@@ -90,12 +97,12 @@ def input_bytes(A):
     return A.numel() * A.element_size()
 
 
-def run(rlu, A, w, precision, steps, warmup, ctx, flags=0):
+def run(rlu, A, w, precision, steps, warmup, ctx, flags=0, extra=None):
     """Warm-up, then `steps` timed decompositions; returns timings and the output.
     The bench owns the device, so the calls say so (RLU_FLAG_EXCLUSIVE: the LU
     panels are ordinary launches instead of cooperative ones)."""
     import torch
-    kw = dict(k=w["k"], l=w["l"], s=w["s"], seed=SEED, ctx=ctx, precision=precision)
+    kw = dict(k=w["k"], l=w["l"], s=w["s"], seed=SEED, ctx=ctx, precision=precision, **(extra or {}))
     if isinstance(A, tuple):
         kw["csr"] = A
         A = None
@@ -230,6 +237,32 @@ def transforms_block(rlu, A, w, ctx, ms_fourier, per_fourier, out_fourier):
     del out
     torch.cuda.empty_cache()
     print(f"# transforms: fourier {ms_fourier:.3f} ms, hadamard {ms:.3f} ms/step", file=sys.stderr, flush=True)
+    return res
+
+
+def second_block(rlu, A, w, ctx, ms_exact, out_exact, shapes=((840, 4096), (420, 2048))):
+    """The headline matrix with B from the paper's second projection Omega_2
+    (k2 x m, SEM width l2; Algorithm 1 steps 4-5) instead of the exact
+    product: time, relative residual, and the Omega_2 pass over A (the
+    contraction stage: gather, transform, transpose) as a rate over A's bytes."""
+    import torch
+    r_exact = rel_residual(A, out_exact)
+    res = {"exact": {"ms_per_step": round(ms_exact, 4), "decomps_per_s": round(1e3 / ms_exact, 3),
+                     "rel_residual": r_exact}}
+    for k2, l2 in shapes:
+        ms, per, out = run(rlu, A, w, "f64", steps=20, warmup=3, ctx=ctx, extra={"k2": k2, "l2": l2})
+        r = rel_residual(A, out)
+        a_bytes = A.numel() * A.element_size()
+        res[f"k2_{k2}_l2_{l2}"] = {
+            "k2": k2, "l2": l2, "ms_per_step": round(ms, 4), "decomps_per_s": round(1e3 / ms, 3),
+            "rel_residual": r, "residual_vs_exact": round(r / r_exact, 4),
+            "omega2_pass_ms": round(per["contract_timed"], 4),
+            "omega2_pass_GBs_over_A": round(a_bytes / (per["contract_timed"] * 1e-3) / 1e9, 1),
+            "stages_ms": {k: round(v, 4) for k, v in per.items() if k != "contract_timed"}}
+        del out
+        torch.cuda.empty_cache()
+        print(f"# second projection k2={k2} l2={l2}: {ms:.3f} ms/step, residual x{r / r_exact:.3f}",
+              file=sys.stderr, flush=True)
     return res
 
 
@@ -390,16 +423,25 @@ def main():
     }
     if ct is not None:
         line["contract"] = ct
-    if not args.no_extras and not is_csr and precision == "f64":
-        line["transforms"] = transforms_block(rlu, A, w, ctx, ms_step, per, out)
+    extras = set() if args.no_extras else {e.strip() for e in args.extras.split(",") if e.strip()}
+    unknown = extras - set(EXTRAS)
+    if unknown:
+        raise SystemExit(f"unknown extras {sorted(unknown)}; choose from {EXTRAS}")
+    if not is_csr and precision == "f64":
+        if "transforms" in extras:
+            line["transforms"] = transforms_block(rlu, A, w, ctx, ms_step, per, out)
+        if "second_projection" in extras:
+            line["second_projection"] = second_block(rlu, A, w, ctx, ms_step, out)
     del out
     if not args.no_cpu_baseline and not is_csr:
         line["cpu_baseline"] = cpu_baseline(A, w)
     del A
     torch.cuda.empty_cache()
-    if not args.no_extras:
+    if "forms" in extras:
         line["forms"] = forms_block(rlu, ctx, dev)
+    if "csr" in extras:
         line["csr"] = csr_block(rlu, ctx, dev)
+    if "serving" in extras:
         line["serving"] = serve_block(rlu, dev)
     print(json.dumps(line), flush=True)
 

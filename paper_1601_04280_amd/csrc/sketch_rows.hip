@@ -77,8 +77,16 @@ __device__ inline double load_nt(const T *p) {
 }
 
 // Z0^T[c, b] = sum over the list of bucket b of sgn_2(i) X[perm[i], c]:
-// S_2 P X, transposed.  Block (bx, by): columns 64 bx .., buckets 64 by ..;
-// wave w sums buckets w, w + 4, ..., lane = column.  X is read once overall.
+// S_2 P X, transposed.  Block (bx, by): columns 64 bx .., buckets 64 by ..,
+// whose list entries are one contiguous range (the list is grouped by
+// bucket).  The block stages that range, kGatherChunk entries at a time, in
+// LDS as (row of X, bucket, sign); each wave then takes a contiguous quarter
+// of the chunk, lane = column, eight independent row reads in flight, and
+// adds each into the tile with an LDS atomic (two waves meet only at a
+// bucket their quarters share).  Every element of X is read once overall.
+constexpr int kGatherChunk = 1024;
+constexpr int kGatherUnroll = 8;
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_omega2_gather(int64_t ncols, const T *__restrict__ X, int64_t ldx,
                                                         const int32_t *__restrict__ perm,
@@ -86,38 +94,54 @@ __global__ void __launch_bounds__(256) k_omega2_gather(int64_t ncols, const T *_
                                                         const uint32_t *__restrict__ list, int l2,
                                                         double *__restrict__ Z0T, int64_t ldz) {
   __shared__ double tile[kTile][kTile + 1];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ int32_t ent_row[kGatherChunk];
+  __shared__ uint8_t ent_meta[kGatherChunk];  // bucket within the tile | sign << 7
+  __shared__ int32_t st_s[kTile + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t c0 = (int64_t)blockIdx.x * kTile, b0 = (int64_t)blockIdx.y * kTile;
+  const int nb = (int)min<int64_t>(kTile, l2 - b0);
   const int64_t col = c0 + lane;
   const bool cok = col < ncols;
   const T *xc = X + (cok ? col : 0);
-  for (int bb = wv; bb < kTile; bb += 4) {
-    const int64_t b = b0 + bb;
-    double acc = 0.0;
-    if (b < l2) {
-      int e = start[b];
-      const int e1 = start[b + 1];
-      for (; e + 4 <= e1; e += 4) {
-        uint32_t c[4];
-        double v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) c[u] = list[e + u];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = cok ? load_nt(xc + (int64_t)perm[c[u] & 0x7FFFFFFFu] * ldx) : 0.0;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc += (c[u] >> 31) ? -v[u] : v[u];
+  for (int i = tid; i < kTile * (kTile + 1); i += 256) (&tile[0][0])[i] = 0.0;
+  if (tid <= nb) st_s[tid] = start[b0 + tid];
+  __syncthreads();
+  const int E0 = st_s[0], E1 = st_s[nb];
+  for (int cb = E0; cb < E1; cb += kGatherChunk) {
+    const int ce = min(kGatherChunk, E1 - cb);
+    for (int t = tid; t < ce; t += 256) {
+      const uint32_t c = list[cb + t];
+      ent_row[t] = perm[c & 0x7FFFFFFFu];
+      // bucket of entry cb + t: the last bb with st_s[bb] <= cb + t
+      int lo = 0, hi = nb - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (st_s[mid] <= cb + t) lo = mid; else hi = mid - 1;
       }
-      for (; e < e1; ++e) {
-        const uint32_t c = list[e];
-        const double v = cok ? load_nt(xc + (int64_t)perm[c & 0x7FFFFFFFu] * ldx) : 0.0;
-        acc += (c >> 31) ? -v : v;
+      ent_meta[t] = (uint8_t)(lo | ((c >> 31) << 7));
+    }
+    __syncthreads();
+    const int per = (ce + 3) >> 2;
+    const int ea = min(ce, wv * per), eb = min(ce, ea + per);
+    for (int e = ea; e < eb; e += kGatherUnroll) {
+      double v[kGatherUnroll];
+#pragma unroll
+      for (int u = 0; u < kGatherUnroll; ++u) {
+        const int eu = min(e + u, eb - 1);
+        v[u] = cok ? load_nt(xc + (int64_t)ent_row[eu] * ldx) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kGatherUnroll; ++u) {
+        if (e + u < eb) {
+          const uint8_t mt = ent_meta[e + u];
+          atomicAdd(&tile[mt & 0x7F][lane], (mt >> 7) ? -v[u] : v[u]);
+        }
       }
     }
-    tile[bb][lane] = acc;
+    __syncthreads();  // the chunk's entries are read before the next chunk is staged
   }
-  __syncthreads();
   const int64_t bo = b0 + lane;
-  if (bo < l2) {
+  if (lane < nb) {
     for (int c = wv; c < kTile; c += 4)
       if (c0 + c < ncols) Z0T[(c0 + c) * ldz + bo] = tile[lane][c];
   }
