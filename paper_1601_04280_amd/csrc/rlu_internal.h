@@ -190,7 +190,7 @@ struct FactorPlan {
   int splits_w, splits_g;
   int splits_i, splits_b;  // G^{-1} = L^{-T} L^{-1} (in parts_g) and B^T = W^T G^{-1} (in parts)
   PrecPlan pp;
-  int k2, l2;  // second projection (k2 > 0), else the exact product
+  int k2 = 0, l2 = 0;  // second projection (k2 > 0), else the exact product
   // offsets (bytes) into the workspace
   size_t ctl, code, sel, twf, twp, Y, slots, csc, Lhat, Uy, Wt, parts, parts_g, Gm, Linv, Dinv, Ginv, Bt,
       Lph, Up, Lt, prec;
