@@ -192,15 +192,20 @@ static rlu_status run_params(const FactorPlan &fp, const rlu_params *p, void *ws
   launch_sem_codes(fp.n, p->s, p->seed, at<uint32_t>(ws, fp.code), nullptr, nullptr, st);
   launch_srft_params(p->s, p->l, p->seed, nullptr, at<int32_t>(ws, fp.sel), at<double2>(ws, fp.twf),
                      at<double2>(ws, fp.twp), st);
-  if (fp.k2 > 0) {  // Omega_2 (step 4): data-independent, drawn with Omega_1
-    hipError_t e2 = launch_omega2_lists(fp.m, fp.l2, p->seed, at<int32_t>(ws, fp.o2start), at<uint32_t>(ws, fp.o2list),
-                                        at<uint32_t>(ws, fp.o2code), st);
-    if (e2 != hipSuccess) return hip_fail(e2, "second projection lists");
-    launch_srft_params(fp.l2, fp.k2, p->seed, nullptr, at<int32_t>(ws, fp.o2sel), at<double2>(ws, fp.o2twf),
-                       at<double2>(ws, fp.o2twp), st, true);
-  }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? RLU_OK : hip_fail(e, "parameter kernels");
+}
+
+// Omega_2's parameters (step 4): bucket lists, codes, selection, twiddles.
+// They depend on nothing but the seed and the shape.
+static rlu_status run_params2(const FactorPlan &fp, const rlu_params *p, void *ws, hipStream_t st) {
+  hipError_t e = launch_omega2_lists(fp.m, fp.l2, p->seed, at<int32_t>(ws, fp.o2start), at<uint32_t>(ws, fp.o2list),
+                                     at<uint32_t>(ws, fp.o2code), st);
+  if (e != hipSuccess) return hip_fail(e, "second projection lists");
+  launch_srft_params(fp.l2, fp.k2, p->seed, nullptr, at<int32_t>(ws, fp.o2sel), at<double2>(ws, fp.o2twf),
+                     at<double2>(ws, fp.o2twp), st, true);
+  e = hipGetLastError();
+  return e == hipSuccess ? RLU_OK : hip_fail(e, "second projection parameters");
 }
 
 
@@ -331,6 +336,7 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(info), 0u, sizeof(rlu_info) / 4, st)) != hipSuccess)
     return hip_fail(e, "fill");
   if ((rs = run_params(fp, p, ws, st)) != RLU_OK) return rs;
+  const bool second = fp.k2 > 0;
   sm.end(RLU_STAGE_PARAMS, st);
 
   double *Y = out->Y ? out->Y : at<double>(ws, fp.Y);
@@ -338,6 +344,13 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   sm.begin(RLU_STAGE_SKETCH, st);
   if ((rs = run_sketch(cx, fp, A, p, Y, ldy, ws, info, st)) != RLU_OK) return rs;
   sm.end(RLU_STAGE_SKETCH, st);
+  if (second) {  // Omega_2's parameters on the auxiliary stream, beside step 3 (whose
+                 // panels leave most CUs idle); the streaming sketch would share its CUs
+    if ((e = hipEventRecord(ax.fork, st)) != hipSuccess || (e = hipStreamWaitEvent(ax.aux, ax.fork, 0)) != hipSuccess)
+      return hip_fail(e, "fork");
+    if ((rs = run_params2(fp, p, ws, ax.aux)) != RLU_OK) return rs;
+    if ((e = hipEventRecord(ax.join, ax.aux)) != hipSuccess) return hip_fail(e, "join");
+  }
 
   // Step 3: P Y = L_y U_y (rows of L_y kept in A's order: Lhat = P^T L_y)
   double *Lhat = at<double>(ws, fp.Lhat);
@@ -354,19 +367,25 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   // to run in several rounds of blocks, the G chain runs on the auxiliary
   // stream beside it; a one-round contraction holds every CU and would only
   // delay the chain (and one of its own blocks), so then the chain runs first.
-  const bool second = fp.k2 > 0;
+  //
+  // With the second projection, M = Omega_2 L_y and its Gram matrix come
+  // first, on the caller's stream: Z's pass over A holds every CU, and M's
+  // short launches queued beside it would wait for them.  The Cholesky chain
+  // after M is latency-bound and runs on the auxiliary stream beside Z's pass.
   const bool hadamard = (p->flags & RLU_FLAG_HADAMARD) != 0;
   const bool overlap = second || A->layout == RLU_CSR || (double)m * (double)n * (double)l >= 1e11;
   hipStream_t gs = overlap ? ax.aux : st;
-  if (overlap) {
+  hipStream_t gram_st = second ? st : gs;  // stream of the Gram stage
+  double *Ms = at<double>(ws, fp.Ms);
+  if (second && (e = hipStreamWaitEvent(st, ax.join, 0)) != hipSuccess) return hip_fail(e, "join");  // parameters
+  if (overlap && !second) {
     if ((e = hipEventRecord(ax.fork, st)) != hipSuccess || (e = hipStreamWaitEvent(ax.aux, ax.fork, 0)) != hipSuccess)
       return hip_fail(e, "fork");
   }
-  sm.begin(RLU_STAGE_GRAM, gs);
-  double *Ms = at<double>(ws, fp.Ms);
+  sm.begin(RLU_STAGE_GRAM, gram_st);
   if (second) {  // M = Omega_2 L_y = Omega_2 P Lhat
     rs = omega2_apply(cx, fp, Lhat, RLU_F64, l, l, out->perm_r, at<double>(ws, fp.M0T), at<double>(ws, fp.MT), Ms,
-                      ctl + 4, hadamard, ws, gs);
+                      ctl + 4, hadamard, ws, gram_st);
     if (rs != RLU_OK) return rs;
   }
   {
@@ -375,10 +394,14 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     g.A = second ? Ms : Lhat; g.lda = l; g.a_dtype = RLU_F64; g.trans_a = true;
     g.B = second ? Ms : Lhat; g.ldb = l;
     g.C = at<double>(ws, fp.Gm); g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
-    e = gemm_f64_splitk(g, fp.splits_g, at<double>(ws, fp.parts_g), gs);
+    e = gemm_f64_splitk(g, fp.splits_g, at<double>(ws, fp.parts_g), gram_st);
     if (e != hipSuccess) return hip_fail(e, "Gram matrix");
   }
-  sm.end(RLU_STAGE_GRAM, gs);
+  sm.end(RLU_STAGE_GRAM, gram_st);
+  if (second) {
+    if ((e = hipEventRecord(ax.fork, st)) != hipSuccess || (e = hipStreamWaitEvent(ax.aux, ax.fork, 0)) != hipSuccess)
+      return hip_fail(e, "fork");
+  }
   sm.begin(RLU_STAGE_CHOL, gs);
   if ((e = launch_chol_inv(l, at<double>(ws, fp.Gm), at<double>(ws, fp.Linv), at<double>(ws, fp.Dinv), info, gs)) != hipSuccess)
     return hip_fail(e, "Cholesky");
