@@ -29,7 +29,10 @@ Unless --no-extras (or a shorter --extras list), the line also carries
            l = k + 10, s = min(n, 8k), 30% BF16-refined, dense
            low-rank-plus-noise (sigma_i = 2^-(i-1), r = 20, noise 1e-10);
            Poisson arrivals at 0.5, 0.7 and 0.9 of the measured saturated
-           rate, p50 / p99 latency (completion - arrival) and decomps/s.
+           rate, p50 / p99 latency (completion - arrival) and decomps/s;
+  `accuracy`: the experiments of Section 4.1 (sigma_1..r = 1, then e^-10 down
+           to e^-200) and 4.2 (sigma from 1 down to e^-100) on 5000 x 5000
+           matrices: ||LU - PAQ||_F against Delta_r and the time, per rank r.
 """
 from __future__ import annotations
 
@@ -42,7 +45,7 @@ import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
-EXTRAS = ("transforms", "second_projection", "forms", "csr", "serving")
+EXTRAS = ("transforms", "second_projection", "forms", "csr", "serving", "accuracy")
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 
 WORKLOADS = {
@@ -266,6 +269,61 @@ def second_block(rlu, A, w, ctx, ms_exact, out_exact, shapes=((840, 4096), (420,
     return res
 
 
+def sweep_params(r, n):
+    """k = r, l = r + 10, s = the power of two at or above 4 l (at most 8192)."""
+    l = r + 10
+    s = 1
+    while s < 4 * l:
+        s *= 2
+    return dict(k=r, l=l, s=min(s, 8192))
+
+
+def accuracy_block(rlu, ctx, dev, n=5000, ranks_41=(50, 100, 200, 300, 400, 500),
+                   ranks_42=(10, 50, 100, 200, 300, 400, 500), steps=3):
+    """The accuracy experiments of Section 4.1 and 4.2 on n x n matrices
+    (singular vectors random): the error ||LU - PAQ||_F against
+    Delta_r = sqrt(sum_{i > r} sigma_i^2) and the time per decomposition.
+    4.1: sigma_1..r = 1, the rest from e^-10 down to e^-200, r varying (the
+    matrix changes with r); 4.2: sigma from 1 down to e^-100, one matrix,
+    rank r varying.  Ranks stop at 500 (l <= 544 in this library)."""
+    import numpy as np
+    import torch
+    import synth
+
+    def one(A, sig, r):
+        p = sweep_params(r, n)
+        out = rlu.factor(A, seed=SEED, ctx=ctx, **p)
+        for _ in range(1):
+            rlu.factor(A, seed=SEED, ctx=ctx, out=out, check=False, **p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rlu.factor(A, seed=SEED, ctx=ctx, out=out, check=False, **p)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        pr, pc = out.perm_r.long(), out.perm_c.long()
+        err = float(torch.linalg.norm(out.L @ out.U - A[pr][:, pc]))
+        delta = float(np.sqrt(np.sum(np.asarray(sig)[r:] ** 2)))
+        return {"r": r, **p, "ms": round(ms, 3), "err_fro": err, "delta_r": delta,
+                "err_over_delta": round(err / delta, 4)}
+
+    res = {"n": n, "sec_4_1": [], "sec_4_2": []}
+    for r in ranks_41:
+        sig = synth.spectrum_step_exp(n, r)
+        A = synth.lowrank_dense_torch(n, n, sig, synth.DATA_SEED_BASE + 41 + r, device=dev)
+        res["sec_4_1"].append(one(A, sig, r))
+        del A
+    sig = synth.spectrum_exp_range(n)
+    A = synth.lowrank_dense_torch(n, n, sig, synth.DATA_SEED_BASE + 42, device=dev)
+    for r in ranks_42:
+        res["sec_4_2"].append(one(A, sig, r))
+    del A
+    torch.cuda.empty_cache()
+    worst = max(x["err_over_delta"] for x in res["sec_4_1"] + res["sec_4_2"])
+    print(f"# accuracy sweeps (n = {n}): worst ||LU - PAQ||_F / Delta_r = {worst}", file=sys.stderr, flush=True)
+    return res
+
+
 def csr_block(rlu, ctx, dev):
     import torch
     name = "csr_200000x100000_planted"
@@ -443,6 +501,8 @@ def main():
         line["csr"] = csr_block(rlu, ctx, dev)
     if "serving" in extras:
         line["serving"] = serve_block(rlu, dev)
+    if "accuracy" in extras:
+        line["accuracy"] = accuracy_block(rlu, ctx, dev)
     print(json.dumps(line), flush=True)
 
 

@@ -149,6 +149,18 @@ def spectrum_exp(count: int, scale: float = 100.0) -> np.ndarray:
     return np.exp(-i / scale)
 
 
+def spectrum_step_exp(n: int, r: int, lo: float = 10.0, hi: float = 200.0) -> np.ndarray:
+    """Section 4.1: sigma_1..r = 1, then n - r values decaying exponentially
+    from e^-lo to e^-hi (exponents evenly spaced)."""
+    return np.concatenate([np.ones(r), np.exp(-np.linspace(lo, hi, n - r))])
+
+
+def spectrum_exp_range(n: int, hi: float = 100.0) -> np.ndarray:
+    """Section 4.2: n values decaying exponentially from 1 to e^-hi
+    (exponents evenly spaced)."""
+    return np.exp(-np.linspace(0.0, hi, n))
+
+
 WORKLOADS = {
     # name: (m, n, k, l, s)
     "dense_1024x512_geometric": (1024, 512, 20, 30, 256),

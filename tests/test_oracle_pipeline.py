@@ -102,3 +102,19 @@ def test_rank_exact_input_is_reproduced_with_hadamard():
     A = synth.lowrank_dense(400, 300, np.linspace(1.0, 0.1, 15), 3)
     res = R.rlu(A, R.Params(15, 20, 64, 7, "hadamard"))
     assert R.residual_fro(A, res.L, res.U, res.perm_r, res.perm_c) <= 1e-12 * np.linalg.norm(A)
+
+
+@pytest.mark.parametrize("section", ["4.1", "4.2"])
+def test_section4_spectra_error_between_tail_norms(section):
+    # Section 4's matrices (singular values given, vectors random): the
+    # rank-l factorization's error lies between Delta_l (Eckart-Young) and a
+    # small multiple of Delta_r (Theorem 3.3).
+    n, r = 400, 20
+    sig = synth.spectrum_step_exp(n, r) if section == "4.1" else synth.spectrum_exp_range(n)
+    A = synth.lowrank_dense(n, n, sig, 11)
+    p = R.Params(r, r + 10, 128, 5)
+    res = R.rlu(A, p)
+    err = R.residual_fro(A, res.L, res.U, res.perm_r, res.perm_c)
+    d_r = np.sqrt(np.sum(sig[r:] ** 2))
+    d_l = np.sqrt(np.sum(sig[r + 10:] ** 2))
+    assert d_l * (1 - 1e-9) <= err <= 10 * d_r
