@@ -44,9 +44,14 @@ def lstsq_product(Lhat: np.ndarray, A) -> np.ndarray:
     return sla.solve_triangular(R, QtA, lower=False)
 
 
-def omega2_apply(X: np.ndarray, h2, sgn2, d2, sel2, l2: int, transform: str = "fourier") -> np.ndarray:
+def omega2_apply(X, h2, sgn2, d2, sel2, l2: int, transform: str = "fourier") -> np.ndarray:
     """Omega_2 X for X with m rows (k_2 x cols): the column-wise form of the
-    sketch of steps 1-2, since (Omega_2 X)^T = X^T Omega_2^T."""
+    sketch of steps 1-2, since (Omega_2 X)^T = X^T Omega_2^T.  X dense, or
+    scipy sparse (then the CSR sketch of X^T)."""
+    if sp.issparse(X):
+        xt = sp.csr_matrix(X.T)
+        cols, rows = xt.shape
+        return sk.sketch_csr(xt.indptr, xt.indices, xt.data, cols, rows, h2, sgn2, d2, sel2, l2, transform).T
     X = np.asarray(X, dtype=np.float64)
     return sk.sketch_dense(np.ascontiguousarray(X.T), h2, sgn2, d2, sel2, l2, transform).T
 
@@ -55,7 +60,8 @@ def sketched_lstsq_product(Ly: np.ndarray, PA: np.ndarray, h2, sgn2, d2, sel2, l
                            transform: str = "fourier"):
     """Algorithm 1 steps 4-5: X = (Omega_2 L_y)^+ Omega_2 P A.
 
-    Ly: m x l in pivoted row order; PA: m x n, the rows of A in that order.
+    Ly: m x l in pivoted row order; PA: m x n (dense or scipy sparse), the
+    rows of A in that order.
     Returns X (l x n) and the two sketches M = Omega_2 L_y, Z = Omega_2 P A.
     """
     M = omega2_apply(Ly, h2, sgn2, d2, sel2, l2, transform)

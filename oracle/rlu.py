@@ -114,8 +114,6 @@ def rlu(A, p: Params, csr=None) -> Result:
     Ly, Uy, perm_r, ipiv_r, zy, gy = lu.gepp(Y)                   # step 3
     extra = {}
     if p.k2:                                                      # steps 4-5 (sketched)
-        if csr is not None:
-            raise ValueError("the second projection is defined here for dense A only")
         h2, sgn2, d2, sel2 = omega2_params(Aop.shape[0], p)
         B, M, Z = lstsq.sketched_lstsq_product(Ly, Aop[perm_r], h2, sgn2, d2, sel2, p.l2, p.transform)
         extra = {"M": M, "Z": Z}

@@ -30,7 +30,8 @@ rlu_status hip_fail(hipError_t e, const char *what) {
 void sketch_dense_set_attrs();
 void sketch_csr_set_attrs();
 
-constexpr int kMaxK2 = 1024;  // rows of Omega_2: the transform kernel's output limit
+constexpr int kMaxK2 = 1024;    // rows of Omega_2: the transform kernel's output limit
+constexpr int kMaxK2Csr = 576;  // the same for the CSR kernel (9 outputs per lane)
 constexpr int kMaxL = 544;  // l x 34 doubles of the Cholesky panel must fit in LDS
 
 // ---------------------------------------------------------------------------
@@ -79,8 +80,8 @@ rlu_status validate_params(const rlu_matrix *A, const rlu_params *p) {
       return fail(RLU_ERR_INVALID_ARG, "need l <= k2 <= min(l2, %d) (l=%d k2=%d l2=%d)", kMaxK2, p->l, p->k2, p->l2);
     if (p->precision != RLU_PREC_F64)
       return fail(RLU_ERR_INVALID_ARG, "the second projection is built for RLU_PREC_F64 only");
-    if (A && A->layout != RLU_DENSE_ROW_MAJOR)
-      return fail(RLU_ERR_INVALID_ARG, "the second projection is built for dense A only");
+    if (A && A->layout == RLU_CSR && p->k2 > kMaxK2Csr)
+      return fail(RLU_ERR_INVALID_ARG, "CSR A: need k2 <= %d for the second projection (k2=%d)", kMaxK2Csr, p->k2);
     if (A && A->m > INT32_MAX) return fail(RLU_ERR_INVALID_ARG, "the second projection needs m < 2^31");
   }
   return RLU_OK;
@@ -171,7 +172,8 @@ rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_pa
   fp->o2sel = cv.take(k2 * 4);
   fp->o2twf = cv.take(second ? std::max<size_t>(1, l2 / 2) * 16 : 0);
   fp->o2twp = cv.take(second ? std::max<size_t>(1, l2 / 2) * 16 : 0);
-  fp->Z0T = cv.take((size_t)n * l2 * 8);
+  fp->o2rowcode = cv.take(second && A->layout == RLU_CSR ? (size_t)m * 4 : 0);
+  fp->Z0T = cv.take(A->layout == RLU_CSR ? 0 : (size_t)n * l2 * 8);
   fp->ZT = cv.take((size_t)n * k2 * 8);
   fp->Zs = cv.take(k2 * (size_t)n * 8);
   fp->M0T = cv.take((size_t)l * l2 * 8);
@@ -427,7 +429,23 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
 
   double *Wt = at<double>(ws, fp.Wt);
   sm.begin(RLU_STAGE_CONTRACT, st);
-  if (second) {  // Z = Omega_2 P A
+  if (second && A->layout == RLU_CSR) {
+    // Z^T = (Omega_2 P A)^T = A^T (Omega_2 P)^T: the CSR sketch of A^T, held
+    // as a CSC copy of A, with Omega_2's codes by row of A
+    CscView cs;
+    if ((e = build_csc(m, n, A->row_ptr, A->col_idx, (const double *)A->values, A->nnz, at<void>(ws, fp.csc),
+                       cx.caps.num_cu, st, &cs)) != hipSuccess)
+      return hip_fail(e, "CSC copy");
+    uint32_t *rowcode = at<uint32_t>(ws, fp.o2rowcode);
+    if ((e = launch_omega2_rowcodes(m, fp.l2, p->seed, out->perm_r, rowcode, st)) != hipSuccess)
+      return hip_fail(e, "second projection codes");
+    e = launch_sketch_csr(n, m, cs.colptr, cs.crow, cs.cval, A->nnz, fp.l2, fp.k2, rowcode, at<int32_t>(ws, fp.o2sel),
+                          at<double2>(ws, fp.o2twf), at<double2>(ws, fp.o2twp), at<double>(ws, fp.ZT), fp.k2,
+                          reinterpret_cast<int32_t *>(ctl + 6), cx.caps.num_cu, hadamard, st);
+    if (e != hipSuccess) return hip_fail(e, "second projection: sparse sketch");
+    if ((e = launch_transpose(n, fp.k2, at<double>(ws, fp.ZT), fp.k2, at<double>(ws, fp.Zs), n, st)) != hipSuccess)
+      return hip_fail(e, "second projection: transpose");
+  } else if (second) {  // Z = Omega_2 P A
     rs = omega2_apply(cx, fp, A->values, A->dtype, A->ld, n, out->perm_r, at<double>(ws, fp.Z0T),
                       at<double>(ws, fp.ZT), at<double>(ws, fp.Zs), ctl + 5, hadamard, ws, st);
     if (rs != RLU_OK) return rs;

@@ -36,6 +36,10 @@ void launch_srft_params(int s, int l, uint64_t seed, int8_t *d, int32_t *sel, do
 // transform step's codes (code2: l2 entries)
 hipError_t launch_omega2_lists(int64_t m, int l2, uint64_t seed, int32_t *start, uint32_t *list,
                                uint32_t *code2, hipStream_t st);
+// Codes of Omega_2's SEM by row of A: code_row[perm[p]] = h_2(p) with bit 31
+// set when sgn_2(p) d_2(h_2(p)) = -1 (p < m, the pivoted position)
+hipError_t launch_omega2_rowcodes(int64_t m, int l2, uint64_t seed, const int32_t *perm, uint32_t *code_row,
+                                  hipStream_t st);
 // Z0T (ncols x l2, ldz) = (S_2 P X)^T for X with m rows (row i of P X is
 // row perm[i] of X); dtype RLU_F64 or RLU_F32
 hipError_t launch_omega2_gather(int64_t ncols, const void *X, int dtype, int64_t ldx, const int32_t *perm,
@@ -59,6 +63,15 @@ hipError_t launch_sketch_csr(int64_t m, int64_t n, const int32_t *row_ptr, const
                              int64_t ldy, int32_t *bad_index, int num_cu, bool hadamard, hipStream_t st);
 hipError_t launch_csr_check(const rlu_matrix *A, int validate_rows, rlu_info *info, hipStream_t st);
 size_t csc_scratch_bytes(int64_t n, int64_t nnz);
+// CSC copy of CSR A in `scratch` (csc_scratch_bytes): column pointers (n + 1),
+// row indices and values; entries of a column in no particular order
+struct CscView {
+  const int32_t *colptr;
+  const int32_t *crow;
+  const double *cval;
+};
+hipError_t build_csc(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                     int64_t nnz, void *scratch, int num_cu, hipStream_t st, CscView *out);
 // W^T (n x l) = A^T Lhat for CSR A, through a CSC copy built in `scratch`
 hipError_t contraction_csr(int64_t m, int64_t n, int l, const int32_t *row_ptr, const int32_t *col,
                            const double *val, int64_t nnz, const double *Lhat, double *Wt, void *scratch,
@@ -198,6 +211,7 @@ struct FactorPlan {
   // (S_2 P A)^T, (Omega_2 P A)^T, Z = Omega_2 P A, the same three for L_y,
   // and M G^{-1}
   size_t o2start, o2list, o2code, o2sel, o2twf, o2twp, Z0T, ZT, Zs, M0T, MT, Ms, Nm;
+  size_t o2rowcode;  // CSR A: Omega_2's codes by row of A
   size_t total;
   size_t sketch_total;
 };

@@ -262,9 +262,8 @@ size_t csc_scratch_bytes(int64_t n, int64_t nnz) {
   return align_up((size_t)(n + 1) * 4, 256) * 3 + align_up((size_t)nnz * 4, 256) + align_up((size_t)nnz * 8, 256);
 }
 
-hipError_t contraction_csr(int64_t m, int64_t n, int l, const int32_t *row_ptr, const int32_t *col,
-                           const double *val, int64_t nnz, const double *Lhat, double *Wt, void *scratch,
-                           int num_cu, hipStream_t st) {
+hipError_t build_csc(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                     int64_t nnz, void *scratch, int num_cu, hipStream_t st, CscView *out) {
   char *w = reinterpret_cast<char *>(scratch);
   const size_t nb4 = align_up((size_t)(n + 1) * 4, 256);
   int32_t *cnt = reinterpret_cast<int32_t *>(w);
@@ -280,7 +279,20 @@ hipError_t contraction_csr(int64_t m, int64_t n, int l, const int32_t *row_ptr, 
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, n, cnt, colptr);
   hipLaunchKernelGGL(k_col_scatter, dim3(rblocks), dim3(256), 0, st, m, n, nnz, row_ptr, col, val, colptr,
                      cursor, crow, cval);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  out->colptr = colptr;
+  out->crow = crow;
+  out->cval = cval;
+  return hipGetLastError();
+}
+
+hipError_t contraction_csr(int64_t m, int64_t n, int l, const int32_t *row_ptr, const int32_t *col,
+                           const double *val, int64_t nnz, const double *Lhat, double *Wt, void *scratch,
+                           int num_cu, hipStream_t st) {
+  CscView cs;
+  hipError_t e = build_csc(m, n, row_ptr, col, val, nnz, scratch, num_cu, st, &cs);
+  if (e != hipSuccess) return e;
+  const int32_t *colptr = cs.colptr, *crow = cs.crow;
+  const double *cval = cs.cval;
   const int qpl = (int)ceil_div(l, 64);
   const int cblocks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 4), (int64_t)num_cu * 16));
 #define RLU_SPMM_Q(Q)                                                                                  \

@@ -9,7 +9,8 @@
 // Z0^T (cols x l_2), so that each column of S_2 P A is one contiguous row.
 // Pi_2 (the SRFT of Section 2.1 down those columns) is then the row sketch
 // kernel run on Z0^T with the identity as its SEM and d_2 folded into the
-// codes.
+// codes.  For CSR A, Omega_2 P A is instead the CSR sketch kernel run on a
+// CSC copy of A (the CSR form of A^T) with Omega_2's codes by row of A.
 #include "rlu_device.h"
 #include "rlu_internal.h"
 
@@ -145,6 +146,25 @@ __global__ void __launch_bounds__(256) k_omega2_gather(int64_t ncols, const T *_
     for (int c = wv; c < kTile; c += 4)
       if (c0 + c < ncols) Z0T[(c0 + c) * ldz + bo] = tile[lane][c];
   }
+}
+
+__global__ void k_omega2_rowcodes(int64_t m, int log2l2, uint64_t key_sem, uint64_t key_signs,
+                                  const int32_t *__restrict__ perm, uint32_t *__restrict__ code_row) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < m; p += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t r = draw(key_sem, (uint64_t)p);
+    const uint32_t b = (uint32_t)(r >> (64 - log2l2));
+    const uint32_t neg = (uint32_t)(r & 1u) ^ (uint32_t)(draw(key_signs, b) >> 63);
+    code_row[perm[p]] = b | (neg << 31);
+  }
+}
+
+hipError_t launch_omega2_rowcodes(int64_t m, int l2, uint64_t seed, const int32_t *perm, uint32_t *code_row,
+                                  hipStream_t st) {
+  if (m < 1 || l2 < 2 || l2 > kMaxS || (l2 & (l2 - 1))) return hipErrorInvalidValue;
+  const int blocks = (int)std::min<int64_t>(1024, ceil_div(m, 256));
+  hipLaunchKernelGGL(k_omega2_rowcodes, dim3(blocks), dim3(256), 0, st, m, ilog2_exact(l2),
+                     stream_key(seed, kStreamSem2), stream_key(seed, kStreamSigns2), perm, code_row);
+  return hipGetLastError();
 }
 
 hipError_t launch_omega2_lists(int64_t m, int l2, uint64_t seed, int32_t *start, uint32_t *list,

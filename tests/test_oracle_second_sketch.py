@@ -104,3 +104,16 @@ def test_streams_of_the_two_projections_differ():
     h1, _ = rng.sem_hash(9, 2000, 256)
     h2, _ = rng.sem_hash(9, 2000, 256, stream=rng.STREAM_SEM2)
     assert np.mean(h1 == h2) < 0.02
+
+
+def test_second_projection_csr_and_dense_agree():
+    import scipy.sparse as sp
+    a = synth.lowrank_dense(300, 200, 0.7 ** np.arange(60), 4, noise=1e-3)
+    a[np.abs(a) < 2e-3] = 0.0           # a sparse pattern
+    c = sp.csr_matrix(a)
+    p = R.Params(8, 16, 64, 3, k2=48, l2=128)
+    d = R.rlu(a, p)
+    s = R.rlu(None, p, csr=(c.indptr, c.indices, c.data, 300, 200))
+    np.testing.assert_array_equal(d.perm_r, s.perm_r)
+    np.testing.assert_array_equal(d.perm_c, s.perm_c)
+    np.testing.assert_allclose(s.B, d.B, rtol=1e-10, atol=1e-12)
