@@ -334,7 +334,15 @@ def csr_block(rlu, ctx, dev):
            "s": w["s"], "ms_per_step": round(ms, 3), "decomps_per_s": round(1e3 / ms, 3),
            "sketch": sketch_rate(A, w, per), "stages_ms": {k: round(v, 4) for k, v in per.items()}}
     print(f"# csr: {ms:.2f} ms/step", file=sys.stderr, flush=True)
-    del A, out
+    del out
+    # the paper's second projection on the same input (time only)
+    k2, l2 = 4 * w["l"], 2048
+    ms2, per2, out2 = run(rlu, A, w, "f64", steps=10, warmup=2, ctx=ctx, extra={"k2": k2, "l2": l2})
+    res["second_projection"] = {"k2": k2, "l2": l2, "ms_per_step": round(ms2, 3),
+                                "decomps_per_s": round(1e3 / ms2, 3),
+                                "stages_ms": {k: round(v, 4) for k, v in per2.items()}}
+    print(f"# csr, second projection k2={k2} l2={l2}: {ms2:.2f} ms/step", file=sys.stderr, flush=True)
+    del A, out2
     torch.cuda.empty_cache()
     return res
 

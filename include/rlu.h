@@ -115,7 +115,7 @@ typedef struct {
   int32_t k2;               /* rows of the second projection Omega_2 of Algorithm 1
                              * steps 4-5; 0 (with l2 = 0): B is the exact product
                              * L_y^+ P A of Corollary 3.2.  Else l <= k2 <= l2,
-                             * k2 <= 1024, dense A, RLU_PREC_F64 only           */
+                             * k2 <= 1024 (CSR A: k2 <= 576), RLU_PREC_F64 only */
   int32_t l2;               /* SEM width of Omega_2: a power of two in [2, 8192]   */
   uint32_t reserved;        /* must be 0                                            */
 } rlu_params;
