@@ -19,7 +19,7 @@ Unless --no-extras (or a shorter --extras list), the line also carries
   `transforms`: the headline matrix sketched with the real Fourier and with
            the Walsh-Hadamard transform (time, sketch rate, residual);
   `second_projection`: the headline matrix with B from the paper's second
-           projection Omega_2 (k2 = 840, l2 = 4096 and k2 = 420, l2 = 2048)
+           projection Omega_2 (k2, l2 = 840, 4096; 840, 2048; 420, 2048)
            in place of the exact product: time, residual against the exact
            product's, and the rate of the Omega_2 pass over A;
   `csr`:   the 200000 x 100000 CSR matrix at 0.1% density with a rank-50
@@ -243,7 +243,7 @@ def transforms_block(rlu, A, w, ctx, ms_fourier, per_fourier, out_fourier):
     return res
 
 
-def second_block(rlu, A, w, ctx, ms_exact, out_exact, shapes=((840, 4096), (420, 2048))):
+def second_block(rlu, A, w, ctx, ms_exact, out_exact, shapes=((840, 4096), (840, 2048), (420, 2048))):
     """The headline matrix with B from the paper's second projection Omega_2
     (k2 x m, SEM width l2; Algorithm 1 steps 4-5) instead of the exact
     product: time, relative residual, and the Omega_2 pass over A (the
