@@ -417,7 +417,7 @@ def serve_block(rlu, dev, counts=(600, 2000, 600), fracs=(0.5, 0.7, 0.9), n_sat=
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
