@@ -150,13 +150,11 @@ enum {
   RLU_STAGE_SKETCH = 1,      /* Y = A Omega^T (step 2)                            */
   RLU_STAGE_LU_Y = 2,        /* row-pivoted LU of Y (step 3)                      */
   RLU_STAGE_CONTRACT = 3,    /* W = Lhat^T A (step 4, the dominant product); with
-                              * k2 > 0, Z = Omega_2 P A instead                   */
+                              * k2 > 0, Z = Omega_2 P A and W = M^T Z instead     */
   RLU_STAGE_GRAM = 4,        /* G = Lhat^T Lhat; with k2 > 0, M = Omega_2 L_y and
                               * G = M^T M                                         */
-  RLU_STAGE_CHOL = 5,        /* inverse Cholesky factor of G and G^{-1} (k2 > 0:
-                              * and M G^{-1})                                     */
-  RLU_STAGE_SOLVE = 6,       /* B^T = W^T G^{-1} (or the refined reduced form;
-                              * k2 > 0: B^T = Z^T M G^{-1})                       */
+  RLU_STAGE_CHOL = 5,        /* inverse Cholesky factor of G and G^{-1}            */
+  RLU_STAGE_SOLVE = 6,       /* B^T = W^T G^{-1} (or the refined reduced form)     */
   RLU_STAGE_LU_B = 7,        /* column-pivoted LU of B (step 5)                   */
   RLU_STAGE_ASSEMBLE = 8,    /* L~, U and L = L_y L~ (step 6)                     */
   RLU_NUM_STAGES = 9

@@ -135,10 +135,10 @@ rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_pa
   fp->l2 = p->l2;
   const bool second = p->k2 > 0;
   const int64_t kc = second ? p->k2 : m;  // depth of the contraction and of the Gram matrix
-  fp->splits_w = second ? 1 : choose_splits(n, l, kc, cx.caps.num_cu);
+  fp->splits_w = choose_splits(n, l, kc, cx.caps.num_cu);
   fp->splits_g = choose_splits(l, l, kc, cx.caps.num_cu);
   fp->splits_i = choose_splits(l, l, l, cx.caps.num_cu);
-  fp->splits_b = choose_splits(n, l, second ? kc : l, cx.caps.num_cu);
+  fp->splits_b = choose_splits(n, l, l, cx.caps.num_cu);
   Carver cv;
   plan_sketch_part(cv, *fp, n, l, p->s);
   fp->sketch_total = cv.off;
@@ -179,7 +179,6 @@ rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_pa
   fp->M0T = cv.take((size_t)l * l2 * 8);
   fp->MT = cv.take((size_t)l * k2 * 8);
   fp->Ms = cv.take(k2 * l * 8);
-  fp->Nm = cv.take(k2 * l * 8);
   fp->total = cv.off;
   return RLU_OK;
 }
@@ -416,14 +415,6 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     if ((e = gemm_f64_splitk(g, fp.splits_i, at<double>(ws, fp.parts_g), gs)) != hipSuccess)
       return hip_fail(e, "inverse Gram");
   }
-  if (second) {  // M G^{-1} (k2 x l), so that B^T = Z^T (M G^{-1})
-    GemmArgs g{};
-    g.M = fp.k2; g.N = l; g.K = l;
-    g.A = Ms; g.lda = l; g.a_dtype = RLU_F64; g.trans_a = false;
-    g.B = at<double>(ws, fp.Ginv); g.ldb = l;
-    g.C = at<double>(ws, fp.Nm); g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
-    if ((e = gemm_f64(g, gs)) != hipSuccess) return hip_fail(e, "M G^{-1}");
-  }
   sm.end(RLU_STAGE_CHOL, gs);
   if (overlap && (e = hipEventRecord(ax.join, ax.aux)) != hipSuccess) return hip_fail(e, "join");
 
@@ -465,6 +456,15 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     e = precision_contract(fp.pp, A, Lhat, l, Wt, at<double>(ws, fp.parts), fp.splits_w, at<void>(ws, fp.prec), st);
     if (e != hipSuccess) return hip_fail(e, "reduced-precision contraction");
   }
+  if (second) {  // W^T = Z^T M (n x l): the normal equations' right-hand side
+    GemmArgs g{};
+    g.M = n; g.N = l; g.K = fp.k2;
+    g.A = at<double>(ws, fp.Zs); g.lda = n; g.a_dtype = RLU_F64; g.trans_a = true;
+    g.B = Ms; g.ldb = l;
+    g.C = Wt; g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
+    if ((e = gemm_f64_splitk(g, fp.splits_w, at<double>(ws, fp.parts), st)) != hipSuccess)
+      return hip_fail(e, "Z^T M");
+  }
   sm.end(RLU_STAGE_CONTRACT, st);
   if (overlap && (e = hipStreamWaitEvent(st, ax.join, 0)) != hipSuccess) return hip_fail(e, "join");
   sm.begin(RLU_STAGE_SOLVE, st);
@@ -472,15 +472,7 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     // one refinement step of the BF16 contraction; writes Bt
     e = precision_refine(fp.pp, A, l, Wt, at<double>(ws, fp.Ginv), at<double>(ws, fp.Bt), at<void>(ws, fp.prec), st);
     if (e != hipSuccess) return hip_fail(e, "refinement");
-  } else if (second) {  // B^T = Z^T (M G^{-1}) = ((Omega_2 L_y)^+ Omega_2 P A)^T
-    GemmArgs g{};
-    g.M = n; g.N = l; g.K = fp.k2;
-    g.A = at<double>(ws, fp.Zs); g.lda = n; g.a_dtype = RLU_F64; g.trans_a = true;
-    g.B = at<double>(ws, fp.Nm); g.ldb = l;
-    g.C = at<double>(ws, fp.Bt); g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
-    if ((e = gemm_f64_splitk(g, fp.splits_b, at<double>(ws, fp.parts), st)) != hipSuccess)
-      return hip_fail(e, "sketched least-squares product");
-  } else {  // B^T = W^T G^{-1}
+  } else {  // B^T = W^T G^{-1}; with k2 > 0, ((Omega_2 L_y)^+ Omega_2 P A)^T
     GemmArgs g{};
     g.M = n; g.N = l; g.K = l;
     g.A = Wt; g.lda = l; g.a_dtype = RLU_F64; g.trans_a = false;

@@ -208,9 +208,8 @@ struct FactorPlan {
   size_t ctl, code, sel, twf, twp, Y, slots, csc, Lhat, Uy, Wt, parts, parts_g, Gm, Linv, Dinv, Ginv, Bt,
       Lph, Up, Lt, prec;
   // second projection: bucket lists and transform parameters of Omega_2,
-  // (S_2 P A)^T, (Omega_2 P A)^T, Z = Omega_2 P A, the same three for L_y,
-  // and M G^{-1}
-  size_t o2start, o2list, o2code, o2sel, o2twf, o2twp, Z0T, ZT, Zs, M0T, MT, Ms, Nm;
+  // (S_2 P A)^T, (Omega_2 P A)^T, Z = Omega_2 P A, and the same three for L_y
+  size_t o2start, o2list, o2code, o2sel, o2twf, o2twp, Z0T, ZT, Zs, M0T, MT, Ms;
   size_t o2rowcode;  // CSR A: Omega_2's codes by row of A
   size_t total;
   size_t sketch_total;
