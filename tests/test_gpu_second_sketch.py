@@ -39,6 +39,9 @@ def screened_second(A, k, l, s, k2, l2, seed, transform="fourier"):
     (700, 300, 8, 16, 64, 16, 16),          # k2 = l = l2: every coordinate kept
     (130, 65, 4, 8, 16, 40, 64),            # fewer rows than two tiles of buckets
     (4100, 129, 10, 12, 32, 64, 8192),      # l2 > m: most buckets empty
+    (300, 200, 1, 2, 8, 2, 2),              # the smallest transform (l2 = 2)
+    (300, 200, 2, 3, 8, 3, 4),
+    (257, 70, 3, 5, 16, 8, 8),              # l2 = 8: the smallest wave-path transform
 ])
 def test_second_projection_matches_oracle(m, n, k, l, s, k2, l2):
     A = synth.lowrank_dense(m, n, 0.8 ** np.arange(min(m, n) // 2), m + n, noise=1e-3)
