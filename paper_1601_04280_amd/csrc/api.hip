@@ -369,10 +369,11 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   // stream beside it; a one-round contraction holds every CU and would only
   // delay the chain (and one of its own blocks), so then the chain runs first.
   //
-  // With the second projection, M = Omega_2 L_y and its Gram matrix come
-  // first, on the caller's stream: Z's pass over A holds every CU, and M's
-  // short launches queued beside it would wait for them.  The Cholesky chain
-  // after M is latency-bound and runs on the auxiliary stream beside Z's pass.
+  // With the second projection (steps 4-5), M = Omega_2 L_y and G = M^T M
+  // come first, on the caller's stream: Z's pass over A holds every CU, and
+  // M's short launches queued beside it would wait for them.  The Cholesky
+  // chain after G is latency-bound and runs on the auxiliary stream beside
+  // Z's pass and W^T = Z^T M; B^T = W^T G^{-1} then ends both forms alike.
   const bool hadamard = (p->flags & RLU_FLAG_HADAMARD) != 0;
   const bool overlap = second || A->layout == RLU_CSR || (double)m * (double)n * (double)l >= 1e11;
   hipStream_t gs = overlap ? ax.aux : st;
