@@ -111,6 +111,25 @@ def test_second_projection_served_matches_direct():
     assert float(torch.linalg.norm(served.L @ served.U - direct.L @ direct.U)) <= 1e-10 * np.linalg.norm(A)
 
 
+def test_second_projection_mixed_served_requests():
+    # exact and sketched products in flight together on the serving streams
+    # (each with its own auxiliary stream), each equal to a direct call
+    reqs = []
+    for i in range(8):
+        A = to_dev(synth.lowrank_dense(600 + 97 * i, 400 + 31 * i, 0.8 ** np.arange(200), 40 + i, noise=1e-3))
+        kw = dict(k=12, l=20, s=64, seed=i + 1)
+        if i % 2:
+            kw.update(k2=64, l2=256)
+        reqs.append((A, kw))
+    direct = [rlu.factor(A, **kw) for A, kw in reqs]
+    with rlu.Server(hbm_budget_bytes=1 << 30, max_inflight=4) as srv:
+        tickets = [srv.submit(A, **kw) for A, kw in reqs]
+        served = [srv.wait(t) for t in tickets]
+    for (A, _), d, g in zip(reqs, direct, served):
+        assert torch.equal(g.perm_r, d.perm_r) and torch.equal(g.perm_c, d.perm_c)
+        assert float(torch.linalg.norm(g.L @ g.U - d.L @ d.U)) <= 1e-10 * float(torch.linalg.norm(A))
+
+
 @pytest.mark.parametrize("kw", [dict(k2=20, l2=64), dict(k2=96, l2=48), dict(k2=96, l2=64),
                                 dict(k2=2048, l2=4096), dict(k2=96, l2=0)])
 def test_second_projection_invalid_arguments(kw):
