@@ -160,7 +160,8 @@ enum {
   RLU_NUM_STAGES = 9
 };
 
-/* Device-side record of one factorization; zeroed by the call that fills it. */
+/* Device-side record of one factorization (8-byte aligned); the call that
+ * fills it clears it first, on its stream. */
 typedef struct {
   int32_t status;           /* rlu_status of the device work (RLU_OK when fine)     */
   int32_t zero_pivots_y;    /* zero pivots in the row-pivoted LU of Y               */
@@ -170,6 +171,15 @@ typedef struct {
   int32_t bad_index;        /* CSR: entries with a column index out of range, plus
                                row_ptr violations (then status = INVALID_ARG)       */
   int32_t reserved[2];
+  /* Pivot screening.  At step j of a pivoted LU the candidates are the
+   * entries of the current column (step 3) or row (step 5); the step's
+   * relative gap is (|c_1| - |c_2|) / |c_1| for its two largest candidate
+   * magnitudes, i.e. 1 - max |multiplier| over the candidates that lost.
+   * min_gap_y / min_gap_b are the smallest gap over the steps of the two LUs
+   * (steps with a single candidate or a zero pivot are skipped; +inf when no
+   * step counts).  A small gap means that rounding could change the pivot. */
+  double min_gap_y;
+  double min_gap_b;         /* +inf from rlu_tall_lu (no column-pivoted LU)       */
 } rlu_info;
 
 typedef struct {

@@ -12,14 +12,16 @@ conventions (pivot ties, zero pivots, parameter generator, real transform).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 from typing import Optional
 
 __all__ = [
-    "RluError", "Context", "Factorization", "Server", "alloc_factors", "workspace_size", "sketch_params", "sketch", "factor",
-    "tall_lu",
+    "RluError", "Context", "Factorization", "Server", "alloc_factors", "alloc_info", "info_dict", "workspace_size",
+    "sketch_params", "sketch", "factor", "tall_lu",
     "library_path", "load_library", "PRECISIONS",
 ]
 
@@ -63,7 +65,25 @@ class Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("zero_pivots_y", ctypes.c_int32),
                 ("zero_pivots_b", ctypes.c_int32), ("nonfinite", ctypes.c_int32),
                 ("timeouts", ctypes.c_int32), ("bad_index", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("reserved", ctypes.c_int32 * 2), ("min_gap_y", ctypes.c_double),
+                ("min_gap_b", ctypes.c_double)]
+
+
+INFO_WORDS = ctypes.sizeof(Info) // 4   # rlu_info as int32 words (device tensor)
+
+
+def info_dict(info) -> dict:
+    """Decode a device rlu_info record (int32 tensor of INFO_WORDS words)."""
+    v = info.cpu()
+    ints = v[:8].tolist()
+    gaps = v[8:12].contiguous().view(_torch().float64).tolist()
+    return {"status": ints[0], "zero_pivots_y": ints[1], "zero_pivots_b": ints[2], "nonfinite": ints[3],
+            "timeouts": ints[4], "bad_index": ints[5], "min_gap_y": gaps[0], "min_gap_b": gaps[1]}
+
+
+def alloc_info(device) -> object:
+    """Storage of one rlu_info record; the call that fills it clears it on its own stream."""
+    return _torch().empty(INFO_WORDS, dtype=_torch().int32, device=device)
 
 
 class Factors(ctypes.Structure):
@@ -133,6 +153,22 @@ def _stream(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
+_open_contexts = weakref.WeakSet()
+
+
+@atexit.register
+def _close_open_contexts():
+    # Interpreter exit: destroy every context (its serving loop, streams and
+    # events) while the HIP runtime is still whole, rather than from __del__
+    # during module teardown, after the runtime's own exit handlers.
+    for c in list(_open_contexts):
+        try:
+            c.close()
+        except Exception:
+            pass
+    _default_ctx.clear()
+
+
 class Context:
     """One rlu_ctx on a device, plus a cached workspace tensor."""
 
@@ -142,6 +178,7 @@ class Context:
         self._h = ctypes.c_void_p()
         _check(lib.rlu_create(device, ctypes.byref(self._h)))
         self._ws = None
+        _open_contexts.add(self)
 
     @property
     def handle(self):
@@ -168,6 +205,7 @@ class Context:
         if self._h:
             load_library().rlu_destroy(self._h)
             self._h = ctypes.c_void_p()
+        self._ws = None
 
     def __del__(self):
         try:
@@ -257,12 +295,10 @@ class Factorization:
     Y: object
     Uy: object
     B: object
-    info: object          # device int32[8] (rlu_info)
+    info: object          # device int32[INFO_WORDS] (rlu_info)
 
     def info_dict(self):
-        v = self.info.cpu().tolist()
-        return {"status": v[0], "zero_pivots_y": v[1], "zero_pivots_b": v[2], "nonfinite": v[3],
-                "timeouts": v[4], "bad_index": v[5]}
+        return info_dict(self.info)
 
 
 def workspace_size(A=None, *, k: int, l: int, s: int, precision: str = "f64", csr=None, ctx: Context = None,
@@ -288,7 +324,7 @@ def alloc_factors(m: int, n: int, l: int, device: int = 0, keep_intermediates: b
         Y=torch.empty(m, l, dtype=f64, device=dev) if keep_intermediates else None,
         Uy=torch.empty(l, l, dtype=f64, device=dev) if keep_intermediates else None,
         B=torch.empty(l, n, dtype=f64, device=dev) if keep_intermediates else None,
-        info=torch.zeros(8, dtype=i32, device=dev))
+        info=alloc_info(dev))
 
 
 def _factors(out: Factorization) -> Factors:
@@ -405,7 +441,7 @@ def tall_lu(X, ctx: Context = None, check: bool = True):
     U = torch.empty(cols, cols, dtype=torch.float64, device=dev)
     perm = torch.empty(rows, dtype=torch.int32, device=dev)
     ipiv = torch.empty(cols, dtype=torch.int32, device=dev)
-    info = torch.zeros(8, dtype=torch.int32, device=dev)
+    info = alloc_info(dev)
     _check(lib.rlu_tall_lu(ctx.handle, X.data_ptr(), rows, cols, X.stride(0), Lhat.data_ptr(), U.data_ptr(),
                            perm.data_ptr(), ipiv.data_ptr(), info.data_ptr(), ws, wsb, _stream(ctx.device)))
     if check and int(info[0].item()) != RLU_OK:

@@ -94,7 +94,7 @@ rlu_status validate_factors(const rlu_matrix *A, const rlu_params *p, const rlu_
   if (out->ldl < p->l) return fail(RLU_ERR_INVALID_ARG, "ldl (%lld) < l (%d)", (long long)out->ldl, p->l);
   if (out->ldu < A->n) return fail(RLU_ERR_INVALID_ARG, "ldu (%lld) < n (%lld)", (long long)out->ldu, (long long)A->n);
   if (out->Y && out->ldy < p->l) return fail(RLU_ERR_INVALID_ARG, "ldy (%lld) < l (%d)", (long long)out->ldy, p->l);
-  if ((reinterpret_cast<uintptr_t>(out->info) & 3)) return fail(RLU_ERR_INVALID_ARG, "info must be 4-byte aligned");
+  if ((reinterpret_cast<uintptr_t>(out->info) & 7)) return fail(RLU_ERR_INVALID_ARG, "info must be 8-byte aligned");
   return RLU_OK;
 }
 
@@ -159,6 +159,7 @@ rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_pa
   fp->Lph = cv.take((size_t)n * l * 8);
   fp->Up = cv.take((size_t)l * l * 8);
   fp->Lt = cv.take((size_t)l * l * 8);
+  fp->gaps = cv.take((size_t)2 * l * 8);
   fp->csc = cv.take(A->layout == RLU_CSR ? csc_scratch_bytes(n, A->nnz) : 0);
   fp->pp = PrecPlan{};
   if (A->layout == RLU_DENSE_ROW_MAJOR && p->precision != RLU_PREC_F64 &&
@@ -509,6 +510,11 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     g.C = out->L; g.ldc = out->ldl; g.alpha = 1.0; g.beta = 0.0;
     if ((e = gemm_f64(g, st)) != hipSuccess) return hip_fail(e, "L = L_y L~");
   }
+  // pivot screening of both LUs (rlu_info.min_gap_y / min_gap_b)
+  unsigned long long *gaps = at<unsigned long long>(ws, fp.gaps);
+  if ((e = launch_pivot_gap(m, l, Lhat, out->perm_r, Uy, gaps, &info->min_gap_y, st)) != hipSuccess ||
+      (e = launch_pivot_gap(n, l, Lph, out->perm_c, Up, gaps + l, &info->min_gap_b, st)) != hipSuccess)
+    return hip_fail(e, "pivot gaps");
   if ((e = launch_finalize(info, abort_flag, st)) != hipSuccess) return hip_fail(e, "finalize");
   sm.end(RLU_STAGE_ASSEMBLE, st);
   return RLU_OK;
@@ -658,6 +664,7 @@ rlu_status rlu_tall_lu_workspace_size(rlu_ctx *ctx, int64_t rows, int64_t cols, 
   Carver cv;
   cv.take(kCtlWords * 4);
   cv.take(gepp_workspace_bytes(rows, (int)cols, gp));
+  cv.take((size_t)cols * 8);
   *bytes = cv.off;
   return RLU_OK;
 }
@@ -669,6 +676,7 @@ rlu_status rlu_tall_lu(rlu_ctx *ctx, const double *X, int64_t rows, int64_t cols
   rlu_status st = rlu_tall_lu_workspace_size(ctx, rows, cols, &need);
   if (st != RLU_OK) return st;
   if (!X || !Lhat || !U || !perm || !info) return fail(RLU_ERR_INVALID_ARG, "NULL matrix argument");
+  if (reinterpret_cast<uintptr_t>(info) & 7) return fail(RLU_ERR_INVALID_ARG, "info must be 8-byte aligned");
   if (ldx < cols) return fail(RLU_ERR_INVALID_ARG, "ldx < cols");
   if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255))
     return fail(RLU_ERR_NO_MEMORY, "workspace must be 256-byte aligned and hold %zu bytes", need);
@@ -679,6 +687,7 @@ rlu_status rlu_tall_lu(rlu_ctx *ctx, const double *X, int64_t rows, int64_t cols
   Carver cv;
   const size_t o_ctl = cv.take(kCtlWords * 4);
   const size_t o_slots = cv.take(gepp_workspace_bytes(rows, (int)cols, gp));
+  const size_t o_gaps = cv.take((size_t)cols * 8);
   hipError_t e = hipSetDevice(cx.caps.device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -689,6 +698,10 @@ rlu_status rlu_tall_lu(rlu_ctx *ctx, const double *X, int64_t rows, int64_t cols
   e = launch_gepp(rows, (int)cols, X, ldx, Lhat, U, perm, ipiv, at<void>(ws, o_slots),
                   reinterpret_cast<int32_t *>(ctl + 1), info, 0, gp, false, s);
   if (e != hipSuccess) return hip_fail(e, "tall LU launch");
+  if ((e = launch_pivot_gap(rows, (int)cols, Lhat, perm, U, at<unsigned long long>(ws, o_gaps), &info->min_gap_y,
+                            s)) != hipSuccess ||
+      (e = launch_store_f64(&info->min_gap_b, __builtin_inf(), s)) != hipSuccess)
+    return hip_fail(e, "pivot gaps");
   if ((e = launch_finalize(info, reinterpret_cast<int32_t *>(ctl + 1), s)) != hipSuccess) return hip_fail(e, "finalize");
   return RLU_OK;
 }

@@ -95,6 +95,73 @@ __global__ void k_finalize(rlu_info *info, const int32_t *abort_flag) {
   }
 }
 
+// Pivot screening (rlu_info.min_gap_*).  At step j of the tall LU the
+// candidates' magnitudes are |x_i| = |L[i][j]| |U[j][j]|, the winner's being
+// |U[j][j]| itself, so the step's top-two gap (|x_1| - |x_2|) / |x_1| is
+// 1 - max |L[i][j]| over the rows that lost.  Lhat holds L in X's row order;
+// rows pivoted earlier hold 0 in column j and the step's own pivot row
+// (perm[j]) holds 1, so that row is skipped.  maxbits[j] receives the
+// column's maximum as the bit pattern of a non-negative double, whose order
+// as an unsigned integer is that of the value (zeroed beforehand).
+__global__ __launch_bounds__(256) void k_gap_colmax(int64_t rows, int l, const double *__restrict__ Lhat,
+                                                    const int32_t *__restrict__ perm, int64_t rows_per_block,
+                                                    unsigned long long *__restrict__ maxbits) {
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = r0 + rows_per_block < rows ? r0 + rows_per_block : rows;
+  for (int c = threadIdx.x; c < l; c += blockDim.x) {
+    const int64_t skip = perm[c];
+    double mx = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+      const double v = fabs(Lhat[r * l + c]);
+      if (r != skip && v > mx) mx = v;
+    }
+    if (mx > 0.0) atomicMax(&maxbits[c], (unsigned long long)__double_as_longlong(mx));
+  }
+}
+
+// min over the counted steps of 1 - maxbits[j]; a step counts when it had
+// another candidate (rows - j > 1) and a nonzero pivot.  One block.
+__global__ __launch_bounds__(256) void k_gap_min(int64_t rows, int l, const double *__restrict__ U,
+                                                 const unsigned long long *__restrict__ maxbits,
+                                                 double *__restrict__ out) {
+  __shared__ double red[256];
+  double g = __longlong_as_double(0x7ff0000000000000ll);  // +inf
+  for (int j = threadIdx.x; j < l; j += blockDim.x) {
+    if (rows - j > 1 && U[(int64_t)j * l + j] != 0.0) {
+      const double v = 1.0 - __longlong_as_double((long long)maxbits[j]);
+      g = v < g ? v : g;
+    }
+  }
+  red[threadIdx.x] = g;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ void k_store_f64(double *p, double v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+hipError_t launch_pivot_gap(int64_t rows, int l, const double *Lhat, const int32_t *perm, const double *U,
+                            unsigned long long *maxbits, double *out, hipStream_t st) {
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(maxbits), 0u, (int64_t)l * 2, st);
+  if (e != hipSuccess) return e;
+  const int64_t rpb = 64;
+  const int blocks = (int)ceil_div(rows, rpb);
+  hipLaunchKernelGGL(k_gap_colmax, dim3(blocks), dim3(256), 0, st, rows, l, Lhat, perm, rpb, maxbits);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gap_min, dim3(1), dim3(256), 0, st, rows, l, U, maxbits, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_store_f64(double *p, double v, hipStream_t st) {
+  hipLaunchKernelGGL(k_store_f64, dim3(1), dim3(64), 0, st, p, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t count, hipStream_t st) {
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(count, 256)));
   hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, st, p, v, count);

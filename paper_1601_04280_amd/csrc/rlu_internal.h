@@ -160,6 +160,12 @@ hipError_t launch_transpose(int64_t rows, int64_t cols, const double *in, int64_
 hipError_t launch_copy_rows(int64_t rows, int64_t cols, const double *in, int64_t ldin,
                             double *out, int64_t ldout, hipStream_t st);
 hipError_t launch_finalize(rlu_info *info, const int32_t *abort_flag, hipStream_t st);
+// *out = the smallest top-two relative pivot gap of a finished tall LU
+// (Lhat rows x l in X's row order, U l x l, perm its row order); maxbits:
+// l words of scratch
+hipError_t launch_pivot_gap(int64_t rows, int l, const double *Lhat, const int32_t *perm, const double *U,
+                            unsigned long long *maxbits, double *out, hipStream_t st);
+hipError_t launch_store_f64(double *p, double v, hipStream_t st);
 
 // ---- context, errors, validation ---------------------------------------------------
 struct ServeState;
@@ -206,7 +212,7 @@ struct FactorPlan {
   int k2 = 0, l2 = 0;  // second projection (k2 > 0), else the exact product
   // offsets (bytes) into the workspace
   size_t ctl, code, sel, twf, twp, Y, slots, csc, Lhat, Uy, Wt, parts, parts_g, Gm, Linv, Dinv, Ginv, Bt,
-      Lph, Up, Lt, prec;
+      Lph, Up, Lt, prec, gaps;
   // second projection: bucket lists and transform parameters of Omega_2,
   // (S_2 P A)^T, (Omega_2 P A)^T, Z = Omega_2 P A, and the same three for L_y
   size_t o2start, o2list, o2code, o2sel, o2twf, o2twp, Z0T, ZT, Zs, M0T, MT, Ms;

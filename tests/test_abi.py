@@ -54,7 +54,7 @@ int main(void) {
   F(rlu_matrix, values); F(rlu_matrix, ld); F(rlu_matrix, nnz);
   F(rlu_params, seed); F(rlu_params, flags); F(rlu_params, k2); F(rlu_params, l2);
   F(rlu_factors, perm_r); F(rlu_factors, Y); F(rlu_factors, info);
-  F(rlu_info, bad_index);
+  F(rlu_info, bad_index); F(rlu_info, min_gap_y); F(rlu_info, min_gap_b);
   return 0;
 }
 """)
@@ -75,6 +75,9 @@ int main(void) {
     assert int(got["rlu_factors.Y"]) == rlu.Factors.Y.offset
     assert int(got["rlu_factors.info"]) == rlu.Factors.info.offset
     assert int(got["rlu_info.bad_index"]) == rlu.Info.bad_index.offset
+    assert int(got["rlu_info.min_gap_y"]) == rlu.Info.min_gap_y.offset
+    assert int(got["rlu_info.min_gap_b"]) == rlu.Info.min_gap_b.offset
+    assert rlu.INFO_WORDS * 4 == int(got["rlu_info"])
     assert int(got["rlu_params.k2"]) == rlu.Params.k2.offset
     assert int(got["rlu_params.l2"]) == rlu.Params.l2.offset
 

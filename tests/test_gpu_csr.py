@@ -14,7 +14,7 @@ import paper_1601_04280_amd as rlu
 import synth
 from oracle import rlu as R
 
-from test_gpu_dense import compare_factors, rel_fro, screened
+from parity import compare_factors, rel_fro, screened
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"

@@ -20,15 +20,7 @@ from oracle import rng as orng
 
 pytestmark = pytest.mark.gpu
 
-DEV = "cuda:0"
-
-
-def to_dev(a):
-    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
-
-
-def rel_fro(a, b):
-    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+from parity import DEV, compare_factors, rel_fro, screened, screened_factor, to_dev
 
 
 # ---------------------------------------------------------------- parameters
@@ -128,6 +120,8 @@ def screened_gaussian(rows, cols, seed):
 def test_tall_lu_matches_oracle(rows, cols, seed):
     y, (L, U, perm, ipiv, zp, gap) = screened_gaussian(rows, cols, seed)
     Lhat, Ug, permg, ipivg, info = rlu.tall_lu(to_dev(y))
+    d = rlu.info_dict(info)
+    assert abs(d["min_gap_y"] - gap) <= 1e-9 and np.isinf(d["min_gap_b"])
     np.testing.assert_array_equal(ipivg.cpu().numpy(), ipiv)
     np.testing.assert_array_equal(permg.cpu().numpy(), perm)
     Lg = Lhat.cpu().numpy()[perm]           # Lhat is in X's own row order
@@ -142,6 +136,8 @@ def test_tall_lu_very_tall(rows, cols, seed):
     matrix."""
     y, (L, U, perm, ipiv, zp, gap) = screened_gaussian(rows, cols, seed)
     Lhat, Ug, permg, ipivg, info = rlu.tall_lu(to_dev(y))
+    d = rlu.info_dict(info)
+    assert abs(d["min_gap_y"] - gap) <= 1e-9 and np.isinf(d["min_gap_b"])
     np.testing.assert_array_equal(ipivg.cpu().numpy(), ipiv)
     np.testing.assert_array_equal(permg.cpu().numpy(), perm)
     Lg = Lhat.cpu().numpy()[perm]
@@ -166,47 +162,6 @@ def test_tall_lu_zero_columns():
 
 
 # ---------------------------------------------------------------- factor
-
-def growth(diag):
-    d = np.abs(diag)
-    return d[0] / np.where(d > 0, d, np.inf)
-
-
-def compare_factors(A, g, o, check_all_columns=False, tol=1e-10):
-    """g: rlu.Factorization (device), o: oracle Result; ``tol`` is the bar of
-    the L columns, U rows and the product (Y stays at 1e-10)."""
-    np.testing.assert_array_equal(g.perm_r.cpu().numpy(), o.perm_r)
-    np.testing.assert_array_equal(g.perm_c.cpu().numpy(), o.perm_c)
-    np.testing.assert_array_equal(g.ipiv_r.cpu().numpy(), o.ipiv_r)
-    np.testing.assert_array_equal(g.ipiv_c.cpu().numpy(), o.ipiv_c)
-    Lg, Ug = g.L.cpu().numpy(), g.U.cpu().numpy()
-    if g.Y is not None:
-        assert rel_fro(g.Y.cpu().numpy(), o.Y) <= 1e-10
-    rho_l = growth(np.diag(o.Uy))
-    rho_u = growth(np.diag(o.U))
-    for j in range(o.L.shape[1]):
-        if check_all_columns or rho_l[j] <= 1e4:
-            assert rel_fro(Lg[:, j], o.L[:, j]) <= tol, (j, rel_fro(Lg[:, j], o.L[:, j]))
-        if check_all_columns or rho_u[j] <= 1e4:
-            assert rel_fro(Ug[j], o.U[j]) <= tol, (j, rel_fro(Ug[j], o.U[j]))
-    assert np.linalg.norm(Lg @ Ug - o.L @ o.U) <= tol * np.linalg.norm(A)
-
-
-def screened(o):
-    """Pivot choices robust to rounding: every top-two gap >= 1e-5, and no pivot
-    down at rounding level (growth rho_j <= 1e9, so u * rho_j <= 1e-7)."""
-    if o.min_gap_y < 1e-5 or o.min_gap_b < 1e-5:
-        return False
-    return growth(np.diag(o.Uy)).max() <= 1e9 and growth(np.diag(o.U)).max() <= 1e9
-
-
-def screened_factor(A, k, l, s, seed):
-    for sd in range(seed, seed + 20):
-        o = R.rlu(A, R.Params(k, l, s, sd))
-        if screened(o):
-            return sd, o
-    raise RuntimeError("no screened seed")
-
 
 def test_factor_small_lowrank_plus_noise():
     A = synth.small_dense()
@@ -318,6 +273,8 @@ def test_factor_zero_matrix():
     info = g.info_dict()
     assert info["zero_pivots_y"] == o.zero_pivots_y == 8
     assert info["zero_pivots_b"] == o.zero_pivots_b == 8
+    assert np.isinf(info["min_gap_y"]) and np.isinf(o.min_gap_y)   # every step a zero pivot
+    assert np.isinf(info["min_gap_b"]) and np.isinf(o.min_gap_b)
     np.testing.assert_array_equal(g.perm_r.cpu().numpy(), o.perm_r)
     np.testing.assert_array_equal(g.perm_c.cpu().numpy(), o.perm_c)
     np.testing.assert_array_equal(g.L.cpu().numpy(), o.L)
@@ -360,7 +317,7 @@ def test_workspace_too_small():
     U = torch.empty(4, 50, dtype=torch.float64, device=DEV)
     pr = torch.empty(60, dtype=torch.int32, device=DEV)
     pc = torch.empty(50, dtype=torch.int32, device=DEV)
-    info = torch.zeros(8, dtype=torch.int32, device=DEV)
+    info = rlu.alloc_info(DEV)
     ws = torch.empty(1024, dtype=torch.uint8, device=DEV)
     f = rlu.Factors(L.data_ptr(), 4, U.data_ptr(), 50, pr.data_ptr(), pc.data_ptr(), None, None, None, 0,
                     None, None, info.data_ptr())

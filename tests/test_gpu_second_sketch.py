@@ -16,7 +16,7 @@ import torch
 import paper_1601_04280_amd as rlu
 import synth
 from oracle import rlu as R
-from test_gpu_dense import DEV, compare_factors, rel_fro, screened, to_dev
+from parity import DEV, compare_factors, rel_fro, screened, to_dev
 
 pytestmark = pytest.mark.gpu
 

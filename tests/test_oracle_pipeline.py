@@ -45,9 +45,34 @@ def test_structure_and_identity_with_range_projection():
     qy, _ = np.linalg.qr(res.Y)
     proj = np.linalg.norm(A - qy @ (qy.T @ A))
     got = R.residual_fro(A, res.L, res.U, res.perm_r, res.perm_c)
-    assert got == pytest.approx(proj, rel=1e-6)
+    # The residual here is ~1.2e-7 ||A||, so the rounding of the two sides
+    # (~1e-16 ||A|| each) bounds their agreement near 1e-9 relative; measured 2e-11.
+    assert got == pytest.approx(proj, rel=1e-9)
     # Eckart-Young lower bound: rank(LU) <= l
     assert got >= R.tail_norm(A, 30) * (1 - 1e-9)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_identity_with_range_projection_large_residual(seed):
+    # A residual of order ||A|| leaves nothing for rounding to cancel: the
+    # identity holds to a few ulps.
+    A = synth.lowrank_dense(300, 200, 0.7 ** np.arange(40), seed, noise=1e-3)
+    res = R.rlu(A, R.Params(10, 16, 64, seed + 1))
+    qy, _ = np.linalg.qr(res.Y)
+    proj = np.linalg.norm(A - qy @ (qy.T @ A))
+    got = R.residual_fro(A, res.L, res.U, res.perm_r, res.perm_c)
+    assert got == pytest.approx(proj, rel=1e-12)
+
+
+def test_tail_norm_hand_values():
+    # Delta_k = sqrt(sum_{i > k} sigma_i^2) for a matrix of known singular
+    # values 5, 4, 3, 2, 1: a signed, permuted diagonal inside a 7 x 6 zero matrix
+    A = np.zeros((7, 6))
+    for r, c, v in [(2, 4, -3.0), (0, 1, 5.0), (6, 0, 1.0), (3, 5, -4.0), (5, 2, 2.0)]:
+        A[r, c] = v
+    want = {0: np.sqrt(55.0), 1: np.sqrt(30.0), 2: np.sqrt(14.0), 3: np.sqrt(5.0), 4: 1.0, 5: 0.0}
+    for k, v in want.items():
+        assert R.tail_norm(A, k) == pytest.approx(v, rel=1e-14, abs=1e-14), k
 
 
 def test_rank_exact_input_is_reproduced():
