@@ -19,8 +19,11 @@ projection Omega_2 (steps 4-5) when asked for:
 5. B  = L_y^+ P A via Householder QR (``lstsq.lstsq_product``), or
    B = (Omega_2 L_y)^+ Omega_2 P A (``lstsq.sketched_lstsq_product``);
 6. B Q = L~ U, LU with column pivoting (``lu.colpiv_lu``);
-7. L  = L_y L~ (``rlu.rlu``).
+7. L  = L_y L~ (``rlu.rlu``);
+
+and, for factors of rank k below the sketch's width, the column selection
+of Y by column pivoting (``colsel``) ahead of step 4.
 
 Every function cites the passage it follows.  Pins: ``tests/test_oracle_*``.
 """
-from . import rng, sketch, lu, lstsq, rlu  # noqa: F401
+from . import rng, sketch, lu, lstsq, colsel, rlu  # noqa: F401

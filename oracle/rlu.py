@@ -15,7 +15,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.sparse as sp
 
-from . import rng, lu, lstsq
+from . import rng, lu, lstsq, colsel
 from . import sketch as sk
 
 
@@ -28,6 +28,7 @@ class Params:
     transform: str = "fourier"   # or "hadamard": the FJL's T (see sketch.py)
     k2: int = 0                  # rows of Omega_2 (0: exact least-squares product)
     l2: int = 0                  # SEM width of Omega_2 (a power of two, k2 <= l2)
+    truncate: bool = False       # rank-k output: k columns of Y by column pivoting (colsel.py)
 
 
 @dataclass
@@ -47,6 +48,8 @@ class Result:
     zero_pivots_b: int = 0
     min_gap_y: float = np.inf
     min_gap_b: float = np.inf
+    ysel: np.ndarray = None      # truncated form: the columns of Y kept, in pivot order
+    min_gap_sel: float = np.inf
     extra: dict = field(default_factory=dict)
 
 
@@ -102,6 +105,10 @@ def rlu(A, p: Params, csr=None) -> Result:
     """Algorithm 1 with B = L_y^+ P A exactly (Corollary 3.2's product) when
     p.k2 == 0, else with B = (Omega_2 L_y)^+ Omega_2 P A (steps 4-5).
 
+    With ``p.truncate`` the factors have rank k (the problem statement of
+    Section 1: L m x k, U k x n): k columns of the sketch Y, chosen by column
+    pivoting (``colsel``), take Y's place from step 3 on.
+
     ``A`` is a dense array, or None with ``csr = (row_ptr, col, val, m, n)``.
     """
     if csr is not None:
@@ -111,7 +118,11 @@ def rlu(A, p: Params, csr=None) -> Result:
     else:
         Aop = np.asarray(A, dtype=np.float64)
     Y = sketch_y(Aop if csr is None else None, p, csr=csr)          # steps 1-2
-    Ly, Uy, perm_r, ipiv_r, zy, gy = lu.gepp(Y)                   # step 3
+    ysel, gsel, Yk = None, np.inf, Y
+    if p.truncate:                                                # rank-k output
+        ysel, _, _, gsel = colsel.pivoted_cholesky_order(Y, p.k)
+        Yk = Y[:, ysel]
+    Ly, Uy, perm_r, ipiv_r, zy, gy = lu.gepp(Yk)                  # step 3
     extra = {}
     if p.k2:                                                      # steps 4-5 (sketched)
         h2, sgn2, d2, sel2 = omega2_params(Aop.shape[0], p)
@@ -124,7 +135,8 @@ def rlu(A, p: Params, csr=None) -> Result:
     L = Ly @ Lt                                                   # step 7
     return Result(L=L, U=U, perm_r=perm_r, perm_c=perm_c, ipiv_r=ipiv_r,
                   ipiv_c=ipiv_c, Y=Y, Ly=Ly, Uy=Uy, B=B, Lt=Lt,
-                  zero_pivots_y=zy, zero_pivots_b=zb, min_gap_y=gy, min_gap_b=gb, extra=extra)
+                  zero_pivots_y=zy, zero_pivots_b=zb, min_gap_y=gy, min_gap_b=gb, ysel=ysel,
+                  min_gap_sel=gsel, extra=extra)
 
 
 def residual_fro(A, L, U, perm_r, perm_c) -> float:
