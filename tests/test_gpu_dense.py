@@ -3,9 +3,9 @@ least-squares product).
 
 Bars: integer parameters and pivot sequences bit-exact (inputs screened so
 every pivot's top-two relative gap is >= 1e-5 in the oracle); Y within 1e-10
-relative (Frobenius); L columns / U rows whose growth factor rho_j =
-|d_0| / |d_j| stays <= 1e4 within 1e-10 relative per column / row (rounding
-in later columns is amplified by rho_j); everything else through the
+relative (Frobenius); L columns / U rows whose growth (the running maximum
+of both LUs' rho_j = |d_0| / |d_j|, see parity.py) keeps u rho <= 1e-12 within 1e-10
+relative per column / row; everything else through the
 product, ||L_g U_g - L_o U_o||_F <= 1e-10 ||A||_F.  On a well-conditioned
 input (sigma_i = 1/i, rank >= l) the 1e-10 bar holds for every column.
 """
