@@ -218,6 +218,22 @@ rlu_status rlu_sketch_params(const rlu_params *p, int64_t n, int32_t *h, int8_t 
 rlu_status rlu_sketch(rlu_ctx *ctx, const rlu_matrix *A, const rlu_params *p, double *Y,
                       int64_t ldy, void *ws, size_t ws_bytes, void *stream);
 
+/* rlu_sketch without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same validation, kernels and result as rlu_sketch;
+ * the scratch (control words, column codes, selection, twiddles) lives in a
+ * fixed device array of RLU_SKETCH_NOALLOC_MAX_BYTES per device, held from
+ * the first rlu_create on that device until the process ends.  The call
+ * allocates nothing: no hipMalloc, hipFree or allocating library routine.
+ * RLU_ERR_NO_MEMORY when the problem needs more scratch than that (the codes
+ * take 4 n bytes, the twiddles 16 s: n up to about two million columns).
+ * Every call on a device shares its array and rewrites what it uses, so
+ * calls that overlap on one device (different streams, threads or contexts)
+ * race; serialise them. */
+#define RLU_SKETCH_NOALLOC_MAX_BYTES ((size_t)8 << 20)
+rlu_status rlu_sketch_noalloc(rlu_ctx *ctx, const rlu_matrix *A, const rlu_params *p, double *Y,
+                              int64_t ldy, void *stream);
+
 /* The whole decomposition (steps 1-6 above); see rlu_factors for outputs. */
 rlu_status rlu_factor(rlu_ctx *ctx, const rlu_matrix *A, const rlu_params *p,
                       const rlu_factors *out, void *ws, size_t ws_bytes, void *stream);

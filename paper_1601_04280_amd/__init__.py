@@ -113,6 +113,7 @@ def load_library():
         "rlu_workspace_size": (I32, [P, ctypes.POINTER(Matrix), ctypes.POINTER(Params), ctypes.POINTER(SZ)]),
         "rlu_sketch_params": (I32, [ctypes.POINTER(Params), I64, P, P, P, P, P]),
         "rlu_sketch": (I32, [P, ctypes.POINTER(Matrix), ctypes.POINTER(Params), P, I64, P, SZ, P]),
+        "rlu_sketch_noalloc": (I32, [P, ctypes.POINTER(Matrix), ctypes.POINTER(Params), P, I64, P]),
         "rlu_factor": (I32, [P, ctypes.POINTER(Matrix), ctypes.POINTER(Params), ctypes.POINTER(Factors),
                               P, SZ, P]),
         "rlu_tall_lu": (I32, [P, P, I64, I64, I64, P, P, P, P, P, P, SZ, P]),
@@ -281,6 +282,22 @@ def sketch(A=None, *, k: int, l: int, s: int, seed: int, csr=None, ctx: Context 
         Y = torch.empty(mat.m, l, dtype=torch.float64, device=f"cuda:{ctx.device}")
     _check(lib.rlu_sketch(ctx.handle, ctypes.byref(mat), ctypes.byref(p), Y.data_ptr(), Y.stride(0), ws,
                           wsb, _stream(ctx.device)))
+    return Y
+
+
+def sketch_noalloc(A=None, *, k: int, l: int, s: int, seed: int, csr=None, ctx: Context = None, Y=None,
+                   flags: int = 0):
+    """``sketch`` through rlu_sketch_noalloc: the library's fixed per-device
+    scratch array instead of a workspace (no device allocation inside the
+    call).  Y (m x l, float64) is allocated here unless the caller passes it."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    mat = _dense_matrix(A) if csr is None else _csr_matrix(*csr)
+    p = _params(k, l, s, seed, flags=flags)
+    if Y is None:
+        Y = torch.empty(mat.m, l, dtype=torch.float64, device=f"cuda:{ctx.device}")
+    _check(load_library().rlu_sketch_noalloc(ctx.handle, ctypes.byref(mat), ctypes.byref(p), Y.data_ptr(),
+                                             Y.stride(0), _stream(ctx.device)))
     return Y
 
 

@@ -3,8 +3,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "rlu_device.h"
 #include "rlu_internal.h"
@@ -520,6 +522,62 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   return RLU_OK;
 }
 
+// ---------------------------------------------------------------------------
+// rlu_sketch and its no-allocation form
+// ---------------------------------------------------------------------------
+// Scratch of rlu_sketch_noalloc: a file-scope device array, one copy per
+// device, alive until the process ends.  Host code never passes its name to a
+// kernel (on the host that name is a stand-in, not a device address): the
+// address comes from hipGetSymbolAddress, taken once per device with that
+// device current (rlu_create), and is kept in every context of the device.
+constexpr size_t kScratchBytes = RLU_SKETCH_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static std::vector<void *> g_scratch_ptr;  // by device
+
+static rlu_status scratch_address(int device, void **out) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize(device + 1, nullptr);
+  if (!g_scratch_ptr[device]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return RLU_OK;
+}
+
+// Validation, the workspace check and the launches of Algorithm 1 steps 1-2.
+// Everything the kernels need beyond A and Y lives in ws (control words, the
+// column codes, the selection and the twiddles), cleared or rewritten by the
+// call itself, so a workspace may be reused by calls that do not overlap.
+static rlu_status sketch_call(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_params *p, double *Y, int64_t ldy,
+                              void *ws, size_t ws_bytes, bool noalloc, void *stream) {
+  rlu_status st = validate_matrix(A);
+  if (st != RLU_OK) return st;
+  if ((st = validate_params(A, p)) != RLU_OK) return st;
+  if (!Y) return fail(RLU_ERR_INVALID_ARG, "Y is NULL");
+  if (ldy < p->l) return fail(RLU_ERR_INVALID_ARG, "ldy (%lld) < l (%d)", (long long)ldy, p->l);
+  FactorPlan fp;
+  Carver cv;
+  plan_sketch_part(cv, fp, A->n, p->l, p->s);
+  fp.n = A->n;
+  fp.m = A->m;
+  if (noalloc && cv.off > ws_bytes)
+    return fail(RLU_ERR_NO_MEMORY,
+                "rlu_sketch_noalloc: this problem needs %zu bytes of scratch, above the fixed %zu (use rlu_sketch "
+                "with a workspace)", cv.off, ws_bytes);
+  if (!ws || ws_bytes < cv.off || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(RLU_ERR_NO_MEMORY, "workspace must be 256-byte aligned and hold %zu bytes", cv.off);
+  hipError_t e = hipSetDevice(cx.caps.device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if ((e = launch_fill_u32(at<uint32_t>(ws, fp.ctl), 0u, kCtlWords, s)) != hipSuccess) return hip_fail(e, "fill");
+  if ((st = run_params(fp, p, ws, s)) != RLU_OK) return st;
+  return run_sketch(cx, fp, A, p, Y, ldy, ws, nullptr, s);
+}
+
 }  // namespace rlu
 
 using namespace rlu;
@@ -551,6 +609,11 @@ rlu_status rlu_create(int device, rlu_ctx **ctx) {
   c->caps.device = device;
   c->caps.num_cu = prop.multiProcessorCount;
   c->caps.max_lds = prop.sharedMemPerBlockOptin ? prop.sharedMemPerBlockOptin : prop.sharedMemPerBlock;
+  rlu_status sst = scratch_address(device, &c->scratch);  // with `device` current
+  if (sst != RLU_OK) {
+    delete c;
+    return sst;
+  }
   sketch_dense_set_attrs();
   sketch_csr_set_attrs();
   *ctx = reinterpret_cast<rlu_ctx *>(c);
@@ -593,25 +656,15 @@ rlu_status rlu_sketch_params(const rlu_params *p, int64_t n, int32_t *h, int8_t 
 rlu_status rlu_sketch(rlu_ctx *ctx, const rlu_matrix *A, const rlu_params *p, double *Y, int64_t ldy,
                       void *ws, size_t ws_bytes, void *stream) {
   if (!ctx) return fail(RLU_ERR_INVALID_ARG, "ctx is NULL");
+  return sketch_call(*reinterpret_cast<rlu_ctx_impl *>(ctx), A, p, Y, ldy, ws, ws_bytes, false, stream);
+}
+
+rlu_status rlu_sketch_noalloc(rlu_ctx *ctx, const rlu_matrix *A, const rlu_params *p, double *Y, int64_t ldy,
+                              void *stream) {
+  if (!ctx) return fail(RLU_ERR_INVALID_ARG, "ctx is NULL");
   rlu_ctx_impl &cx = *reinterpret_cast<rlu_ctx_impl *>(ctx);
-  rlu_status st = validate_matrix(A);
-  if (st != RLU_OK) return st;
-  if ((st = validate_params(A, p)) != RLU_OK) return st;
-  if (!Y) return fail(RLU_ERR_INVALID_ARG, "Y is NULL");
-  if (ldy < p->l) return fail(RLU_ERR_INVALID_ARG, "ldy (%lld) < l (%d)", (long long)ldy, p->l);
-  FactorPlan fp;
-  Carver cv;
-  plan_sketch_part(cv, fp, A->n, p->l, p->s);
-  fp.n = A->n;
-  fp.m = A->m;
-  if (!ws || ws_bytes < cv.off || (reinterpret_cast<uintptr_t>(ws) & 255))
-    return fail(RLU_ERR_NO_MEMORY, "workspace must be 256-byte aligned and hold %zu bytes", cv.off);
-  hipError_t e = hipSetDevice(cx.caps.device);
-  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if ((e = launch_fill_u32(at<uint32_t>(ws, fp.ctl), 0u, kCtlWords, s)) != hipSuccess) return hip_fail(e, "fill");
-  if ((st = run_params(fp, p, ws, s)) != RLU_OK) return st;
-  return run_sketch(cx, fp, A, p, Y, ldy, ws, nullptr, s);
+  if (!cx.scratch) return fail(RLU_ERR_DEVICE, "the context has no scratch address");
+  return sketch_call(cx, A, p, Y, ldy, cx.scratch, kScratchBytes, true, stream);
 }
 
 rlu_status rlu_factor(rlu_ctx *ctx, const rlu_matrix *A, const rlu_params *p, const rlu_factors *out,

@@ -189,6 +189,7 @@ struct AuxStream {
 };
 struct rlu_ctx_impl {
   DevCaps caps{};
+  void *scratch = nullptr;  // this device's copy of the no-allocation scratch array
   ServeState *serve = nullptr;
   StageTimer timer;
   std::mutex aux_mu;
