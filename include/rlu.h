@@ -107,15 +107,21 @@ typedef struct {
 
 typedef struct {
   int32_t k;                /* target rank of the error reference, 1 <= k <= l      */
-  int32_t l;                /* sketch columns = rank of the factors, l <= min(m, n) */
-  int32_t s;                /* SEM width: a power of two in [2, 8192], s >= l       */
+  int32_t l;                /* sketch columns = rank of the factors,
+                             * l <= min(m, n, 1024)                                 */
+  int32_t s;                /* SEM width: a power of two in [2, 65536], s >= l.
+                             * Up to 8192 the transform runs on each row's s
+                             * buckets in LDS; above, the projection is formed
+                             * explicitly (n x l FP64 in the workspace) and
+                             * Y = A Omega^T runs on the FP64 GEMM (dense A), or
+                             * the cos table is read from global memory (CSR A) */
   int32_t precision;        /* rlu_precision                                        */
   uint64_t seed;            /* seed of the random parameters                        */
   uint32_t flags;           /* RLU_FLAG_* bits                                      */
   int32_t k2;               /* rows of the second projection Omega_2 of Algorithm 1
                              * steps 4-5; 0 (with l2 = 0): B is the exact product
                              * L_y^+ P A of Corollary 3.2.  Else l <= k2 <= l2,
-                             * k2 <= 1024 (CSR A: k2 <= 576), RLU_PREC_F64 only */
+                             * k2 <= 1024, RLU_PREC_F64 only                      */
   int32_t l2;               /* SEM width of Omega_2: a power of two in [2, 8192]   */
   uint32_t reserved;        /* must be 0                                            */
 } rlu_params;
@@ -140,6 +146,28 @@ typedef struct {
                                 * (the subsampled randomized Hadamard transform of Section 4),
                                 * instead of the orthonormal real Fourier transform; the
                                 * signs, the selection and the sparse embedding are the same */
+#define RLU_FLAG_DETERMINISTIC 32u /* bitwise-reproducible results: every sum the call forms is
+                                    * taken in an order fixed by the inputs alone, so two calls
+                                    * with the same A and parameters give identical bits (on the
+                                    * same device and library build).  The dense sketch adds each
+                                    * bucket's columns in ascending column order (the order of the
+                                    * SEM's definition, Section 2.2) from bucket-sorted tables built
+                                    * per call (workspace grows by about 4 n + 4 (s + 1) n / C bytes,
+                                    * C = min(s, 8192)); the sparse contraction sorts each column's
+                                    * entries of its CSC copy by row; the second projection sums
+                                    * each bucket's rows in position order.  Slower than the default
+                                    * atomic accumulation, whose results agree with these to
+                                    * rounding; the pivots are the same on screened inputs. */
+#define RLU_FLAG_TRUNCATE 64u /* factors of rank k instead of l (the problem statement of
+                              * Section 1: L m x k, U k x n).  The sketch Y keeps its l
+                              * columns; k of them are chosen by column pivoting (the first
+                              * k pivots of Y's column-pivoted QR, Businger & Golub 1965,
+                              * taken as pivoted Cholesky of Y^T Y), and steps 3-6 run on
+                              * those k columns, so every output sized by l above (L, U,
+                              * U_y, B, ipiv_r, ipiv_c) is sized by k instead; Y stays
+                              * m x l.  Keeps the oversampling: the k columns are the ones
+                              * that best span Y's range greedily, where truncating L_y to
+                              * its first k columns would equal a k-column sketch. */
 #define RLU_FLAG_TIMING_CONTRACT 8u /* events around the contraction stage only (one stage
                                      * boundary instead of nine; rlu_stage_times reports the
                                      * other stages as 0 for such calls) */
@@ -170,7 +198,9 @@ typedef struct {
   int32_t timeouts;         /* device-wide barriers that gave up (then status != 0) */
   int32_t bad_index;        /* CSR: entries with a column index out of range, plus
                                row_ptr violations (then status = INVALID_ARG)       */
-  int32_t reserved[2];
+  int32_t zero_pivots_sel;  /* RLU_FLAG_TRUNCATE: column-selection steps whose
+                               remaining columns had no positive norm left          */
+  int32_t reserved;
   /* Pivot screening.  At step j of a pivoted LU the candidates are the
    * entries of the current column (step 3) or row (step 5); the step's
    * relative gap is (|c_1| - |c_2|) / |c_1| for its two largest candidate
@@ -193,6 +223,8 @@ typedef struct {
   double *Uy;               /* optional (NULL): U_y, l x l, leading dimension l     */
   double *B;                /* optional (NULL): B = L_y^+ P A (k2 > 0: the sketched
                              * product of steps 4-5), l x n, ld n                  */
+  int32_t *ysel;            /* optional (NULL), RLU_FLAG_TRUNCATE only: the k columns
+                             * of Y kept, in the order chosen                       */
   rlu_info *info;           /* required: device record, see rlu_info                */
 } rlu_factors;
 
@@ -277,6 +309,15 @@ rlu_status rlu_submit(rlu_ctx *ctx, const rlu_matrix *A, const rlu_params *p,
 /* RLU_OK when the ticket's results are complete, RLU_ERR_AGAIN while it is
  * pending, or the ticket's own error.  A terminal status retires the ticket. */
 rlu_status rlu_poll(rlu_ctx *ctx, uint64_t ticket);
+
+/* Counters of the serving loop (host out-param, 8 words): [0] 1 when the
+ * loop has one slot, whose requests run with the device to themselves (LU
+ * panels as ordinary launches, each request's stages as one HIP graph),
+ * [1] compute units the requests are planned for, [2] requests launched as
+ * graphs, [3] of those, graphs updated in place, [4] graphs instantiated,
+ * [5] requests enqueued directly because capture or instantiation failed,
+ * [6..7] 0. */
+rlu_status rlu_serve_stats(rlu_ctx *ctx, uint64_t *stats);
 
 /* Wait for all admitted requests, then stop and free the pool. */
 rlu_status rlu_serve_stop(rlu_ctx *ctx);

@@ -40,6 +40,8 @@ RLU_FLAG_TIMING = 2
 RLU_FLAG_EXCLUSIVE = 4
 RLU_FLAG_TIMING_CONTRACT = 8
 RLU_FLAG_HADAMARD = 16
+RLU_FLAG_DETERMINISTIC = 32
+RLU_FLAG_TRUNCATE = 64
 STAGES = ["params", "sketch", "lu_y", "contract", "gram", "chol", "solve", "lu_b", "assemble"]
 
 
@@ -65,7 +67,7 @@ class Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("zero_pivots_y", ctypes.c_int32),
                 ("zero_pivots_b", ctypes.c_int32), ("nonfinite", ctypes.c_int32),
                 ("timeouts", ctypes.c_int32), ("bad_index", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2), ("min_gap_y", ctypes.c_double),
+                ("zero_pivots_sel", ctypes.c_int32), ("reserved", ctypes.c_int32), ("min_gap_y", ctypes.c_double),
                 ("min_gap_b", ctypes.c_double)]
 
 
@@ -78,7 +80,8 @@ def info_dict(info) -> dict:
     ints = v[:8].tolist()
     gaps = v[8:12].contiguous().view(_torch().float64).tolist()
     return {"status": ints[0], "zero_pivots_y": ints[1], "zero_pivots_b": ints[2], "nonfinite": ints[3],
-            "timeouts": ints[4], "bad_index": ints[5], "min_gap_y": gaps[0], "min_gap_b": gaps[1]}
+            "timeouts": ints[4], "bad_index": ints[5], "zero_pivots_sel": ints[6],
+            "min_gap_y": gaps[0], "min_gap_b": gaps[1]}
 
 
 def alloc_info(device) -> object:
@@ -91,7 +94,7 @@ class Factors(ctypes.Structure):
                 ("ldu", ctypes.c_int64), ("perm_r", ctypes.c_void_p), ("perm_c", ctypes.c_void_p),
                 ("ipiv_r", ctypes.c_void_p), ("ipiv_c", ctypes.c_void_p), ("Y", ctypes.c_void_p),
                 ("ldy", ctypes.c_int64), ("Uy", ctypes.c_void_p), ("B", ctypes.c_void_p),
-                ("info", ctypes.c_void_p)]
+                ("ysel", ctypes.c_void_p), ("info", ctypes.c_void_p)]
 
 
 _lib = None
@@ -123,6 +126,7 @@ def load_library():
                               ctypes.POINTER(U64)]),
         "rlu_poll": (I32, [P, U64]),
         "rlu_serve_stop": (I32, [P]),
+        "rlu_serve_stats": (I32, [P, ctypes.POINTER(U64)]),
         "rlu_stage_times": (I32, [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(I32)]),
         "rlu_last_error": (ctypes.c_char_p, []),
     }
@@ -313,6 +317,7 @@ class Factorization:
     Uy: object
     B: object
     info: object          # device int32[INFO_WORDS] (rlu_info)
+    ysel: object = None   # RLU_FLAG_TRUNCATE: the k columns of Y kept
 
     def info_dict(self):
         return info_dict(self.info)
@@ -329,25 +334,30 @@ def workspace_size(A=None, *, k: int, l: int, s: int, precision: str = "f64", cs
     return nbytes.value
 
 
-def alloc_factors(m: int, n: int, l: int, device: int = 0, keep_intermediates: bool = False) -> Factorization:
-    """Output buffers of one decomposition on the device."""
+def alloc_factors(m: int, n: int, l: int, device: int = 0, keep_intermediates: bool = False,
+                  rank: int = None) -> Factorization:
+    """Output buffers of one decomposition on the device: factors of rank
+    ``rank`` (k for RLU_FLAG_TRUNCATE; l by default) from an l-column sketch."""
     torch = _torch()
     dev = f"cuda:{device}"
     f64, i32 = torch.float64, torch.int32
+    r = l if rank is None else rank
     return Factorization(
-        L=torch.empty(m, l, dtype=f64, device=dev), U=torch.empty(l, n, dtype=f64, device=dev),
+        L=torch.empty(m, r, dtype=f64, device=dev), U=torch.empty(r, n, dtype=f64, device=dev),
         perm_r=torch.empty(m, dtype=i32, device=dev), perm_c=torch.empty(n, dtype=i32, device=dev),
-        ipiv_r=torch.empty(l, dtype=i32, device=dev), ipiv_c=torch.empty(l, dtype=i32, device=dev),
+        ipiv_r=torch.empty(r, dtype=i32, device=dev), ipiv_c=torch.empty(r, dtype=i32, device=dev),
         Y=torch.empty(m, l, dtype=f64, device=dev) if keep_intermediates else None,
-        Uy=torch.empty(l, l, dtype=f64, device=dev) if keep_intermediates else None,
-        B=torch.empty(l, n, dtype=f64, device=dev) if keep_intermediates else None,
-        info=alloc_info(dev))
+        Uy=torch.empty(r, r, dtype=f64, device=dev) if keep_intermediates else None,
+        B=torch.empty(r, n, dtype=f64, device=dev) if keep_intermediates else None,
+        info=alloc_info(dev),
+        ysel=torch.empty(r, dtype=i32, device=dev) if rank is not None else None)
 
 
 def _factors(out: Factorization) -> Factors:
     return Factors(out.L.data_ptr(), out.L.stride(0), out.U.data_ptr(), out.U.stride(0), out.perm_r.data_ptr(),
                    out.perm_c.data_ptr(), _ptr(out.ipiv_r), _ptr(out.ipiv_c), _ptr(out.Y),
-                   out.Y.stride(0) if out.Y is not None else 0, _ptr(out.Uy), _ptr(out.B), out.info.data_ptr())
+                   out.Y.stride(0) if out.Y is not None else 0, _ptr(out.Uy), _ptr(out.B), _ptr(out.ysel),
+                   out.info.data_ptr())
 
 
 def factor(A=None, *, k: int, l: int, s: int, seed: int, precision: str = "f64", csr=None,
@@ -367,7 +377,8 @@ def factor(A=None, *, k: int, l: int, s: int, seed: int, precision: str = "f64",
     _check(lib.rlu_workspace_size(ctx.handle, ctypes.byref(mat), ctypes.byref(p), ctypes.byref(nbytes)))
     ws, wsb = ctx.workspace(nbytes.value)
     if out is None:
-        out = alloc_factors(m, n, l, ctx.device, keep_intermediates)
+        out = alloc_factors(m, n, l, ctx.device, keep_intermediates,
+                            rank=k if flags & RLU_FLAG_TRUNCATE else None)
     f = _factors(out)
     _check(lib.rlu_factor(ctx.handle, ctypes.byref(mat), ctypes.byref(p), ctypes.byref(f), ws, wsb,
                           _stream(ctx.device)))
@@ -395,12 +406,13 @@ class Server:
 
     def submit(self, A=None, *, k: int, l: int, s: int, seed: int, precision: str = "f64", csr=None,
                out: Factorization = None, keep_intermediates: bool = False, sync_inputs: bool = True,
-               k2: int = 0, l2: int = 0) -> int:
+               k2: int = 0, l2: int = 0, flags: int = 0) -> int:
         torch = _torch()
         mat = _dense_matrix(A) if csr is None else _csr_matrix(*csr)
-        p = _params(k, l, s, seed, precision, 0, k2, l2)
+        p = _params(k, l, s, seed, precision, flags, k2, l2)
         if out is None:
-            out = alloc_factors(mat.m, mat.n, l, self.ctx.device, keep_intermediates)
+            out = alloc_factors(mat.m, mat.n, l, self.ctx.device, keep_intermediates,
+                                rank=k if flags & RLU_FLAG_TRUNCATE else None)
         if sync_inputs:
             torch.cuda.current_stream(self.ctx.device).synchronize()
         f = _factors(out)
@@ -429,6 +441,13 @@ class Server:
             if time.perf_counter() - t0 > timeout_s:
                 raise TimeoutError(f"ticket {ticket} not complete after {timeout_s} s")
             time.sleep(20e-6)
+
+    def stats(self) -> dict:
+        """Serving-loop counters (rlu_serve_stats)."""
+        v = (ctypes.c_uint64 * 8)()
+        _check(load_library().rlu_serve_stats(self.ctx.handle, v))
+        return {"exclusive_slot": bool(v[0]), "cus": int(v[1]), "graph_launches": int(v[2]),
+                "graph_updates": int(v[3]), "graph_builds": int(v[4]), "direct_fallbacks": int(v[5])}
 
     def stop(self):
         if self._running:

@@ -32,14 +32,16 @@ rlu_status hip_fail(hipError_t e, const char *what) {
 void sketch_dense_set_attrs();
 void sketch_csr_set_attrs();
 
-constexpr int kMaxK2 = 1024;    // rows of Omega_2: the transform kernel's output limit
-constexpr int kMaxK2Csr = 576;  // the same for the CSR kernel (9 outputs per lane)
-constexpr int kMaxL = 544;  // l x 34 doubles of the Cholesky panel must fit in LDS
+constexpr int kMaxK2 = 1024;  // rows of Omega_2: the transform kernels' output limit
 
 // ---------------------------------------------------------------------------
 // validation
 // ---------------------------------------------------------------------------
 static bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+static bool deterministic(const rlu_params *p) { return (p->flags & RLU_FLAG_DETERMINISTIC) != 0; }
+static bool truncated(const rlu_params *p) { return (p->flags & RLU_FLAG_TRUNCATE) != 0; }
+// rank of the factors: k columns of Y kept with RLU_FLAG_TRUNCATE, else all l
+static int factor_rank(const rlu_params *p) { return truncated(p) ? p->k : p->l; }
 
 rlu_status validate_matrix(const rlu_matrix *A) {
   if (!A) return fail(RLU_ERR_INVALID_ARG, "A is NULL");
@@ -74,16 +76,14 @@ rlu_status validate_params(const rlu_matrix *A, const rlu_params *p) {
   if (p->l > kMaxL) return fail(RLU_ERR_INVALID_ARG, "l (%d) exceeds the supported maximum %d", p->l, kMaxL);
   if (p->precision < RLU_PREC_F64 || p->precision > RLU_PREC_BF16_REFINED) return fail(RLU_ERR_INVALID_ARG, "unknown precision %d", p->precision);
   if (p->flags & ~(RLU_FLAG_VALIDATE | RLU_FLAG_TIMING | RLU_FLAG_EXCLUSIVE | RLU_FLAG_TIMING_CONTRACT |
-                   RLU_FLAG_HADAMARD)) return fail(RLU_ERR_INVALID_ARG, "unknown flag bits 0x%x", p->flags);
+                   RLU_FLAG_HADAMARD | RLU_FLAG_DETERMINISTIC | RLU_FLAG_TRUNCATE)) return fail(RLU_ERR_INVALID_ARG, "unknown flag bits 0x%x", p->flags);
   if (p->k2 != 0 || p->l2 != 0) {  // the second projection of steps 4-5
-    if (p->l2 < 2 || p->l2 > kMaxS || !is_pow2(p->l2))
-      return fail(RLU_ERR_INVALID_ARG, "l2 (%d) must be a power of two in [2, %d]", p->l2, kMaxS);
+    if (p->l2 < 2 || p->l2 > kMaxL2 || !is_pow2(p->l2))
+      return fail(RLU_ERR_INVALID_ARG, "l2 (%d) must be a power of two in [2, %d]", p->l2, kMaxL2);
     if (p->k2 < p->l || p->k2 > p->l2 || p->k2 > kMaxK2)
       return fail(RLU_ERR_INVALID_ARG, "need l <= k2 <= min(l2, %d) (l=%d k2=%d l2=%d)", kMaxK2, p->l, p->k2, p->l2);
     if (p->precision != RLU_PREC_F64)
       return fail(RLU_ERR_INVALID_ARG, "the second projection is built for RLU_PREC_F64 only");
-    if (A && A->layout == RLU_CSR && p->k2 > kMaxK2Csr)
-      return fail(RLU_ERR_INVALID_ARG, "CSR A: need k2 <= %d for the second projection (k2=%d)", kMaxK2Csr, p->k2);
     if (A && A->m > INT32_MAX) return fail(RLU_ERR_INVALID_ARG, "the second projection needs m < 2^31");
   }
   return RLU_OK;
@@ -93,7 +93,9 @@ rlu_status validate_factors(const rlu_matrix *A, const rlu_params *p, const rlu_
   if (!out) return fail(RLU_ERR_INVALID_ARG, "factors is NULL");
   if (!out->L || !out->U || !out->perm_r || !out->perm_c) return fail(RLU_ERR_INVALID_ARG, "L, U, perm_r and perm_c are required");
   if (!out->info) return fail(RLU_ERR_INVALID_ARG, "info (device record) is required");
-  if (out->ldl < p->l) return fail(RLU_ERR_INVALID_ARG, "ldl (%lld) < l (%d)", (long long)out->ldl, p->l);
+  if (out->ldl < factor_rank(p))
+    return fail(RLU_ERR_INVALID_ARG, "ldl (%lld) < the factors' rank (%d)", (long long)out->ldl, factor_rank(p));
+  if (out->ysel && !truncated(p)) return fail(RLU_ERR_INVALID_ARG, "ysel is an output of RLU_FLAG_TRUNCATE only");
   if (out->ldu < A->n) return fail(RLU_ERR_INVALID_ARG, "ldu (%lld) < n (%lld)", (long long)out->ldu, (long long)A->n);
   if (out->Y && out->ldy < p->l) return fail(RLU_ERR_INVALID_ARG, "ldy (%lld) < l (%d)", (long long)out->ldy, p->l);
   if ((reinterpret_cast<uintptr_t>(out->info) & 7)) return fail(RLU_ERR_INVALID_ARG, "info must be 8-byte aligned");
@@ -115,36 +117,54 @@ struct Carver {
 // control words: [1] abort flag of the cooperative launches
 constexpr int kCtlWords = 64;
 
-static void plan_sketch_part(Carver &cv, FactorPlan &fp, int64_t n, int l, int s) {
+
+static void plan_sketch_part(Carver &cv, FactorPlan &fp, const rlu_matrix *A, const rlu_params *p) {
+  const int64_t n = A->n;
+  const int l = p->l, s = p->s;
   fp.ctl = cv.take(kCtlWords * 4);
   fp.code = cv.take((size_t)n * 4);
   fp.sel = cv.take((size_t)l * 4);
   fp.twf = cv.take((size_t)std::max(1, s / 2) * 16);
   fp.twp = cv.take((size_t)std::max(1, s / 2) * 16);
+  const bool dense = A->layout == RLU_DENSE_ROW_MAJOR, wide = s > kLdsMaxS;
+  // bucket-ordered tables of the deterministic dense sketch (the explicit
+  // projection of wide s sums in a fixed order already)
+  fp.ordt = cv.take(deterministic(p) && dense && !wide ? ordered_tables_bytes(n, s) : 0);
+  // wide s: the cos table in global memory, and the explicit n x l projection
+  fp.ctabg = cv.take(wide && !(p->flags & RLU_FLAG_HADAMARD) ? (size_t)s * 8 : 0);
+  fp.omt = cv.take(wide && dense ? (size_t)n * l * 8 : 0);
 }
 
-rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_params *p, FactorPlan *fp) {
+rlu_status plan_factor(const DevCaps &caps, const rlu_matrix *A, const rlu_params *p, FactorPlan *fp) {
   std::string why;
   fp->m = A->m;
   fp->n = A->n;
-  fp->l = p->l;
+  fp->ls = p->l;
+  fp->l = factor_rank(p);  // k with RLU_FLAG_TRUNCATE, else l
   fp->s = p->s;
-  if (!plan_gepp(A->m, p->l, cx.caps, &fp->py, &why)) return fail(RLU_ERR_INVALID_ARG, "row-pivoted LU: %s", why.c_str());
-  if (!plan_gepp(A->n, p->l, cx.caps, &fp->pb, &why)) return fail(RLU_ERR_INVALID_ARG, "column-pivoted LU: %s", why.c_str());
   const int64_t m = A->m, n = A->n;
-  const int l = p->l;
+  const int l = fp->l, ls = fp->ls;
+  if (!plan_gepp(m, l, caps, &fp->py, &why)) return fail(RLU_ERR_INVALID_ARG, "row-pivoted LU: %s", why.c_str());
+  if (!plan_gepp(n, l, caps, &fp->pb, &why)) return fail(RLU_ERR_INVALID_ARG, "column-pivoted LU: %s", why.c_str());
   fp->k2 = p->k2;
   fp->l2 = p->l2;
   const bool second = p->k2 > 0;
   const int64_t kc = second ? p->k2 : m;  // depth of the contraction and of the Gram matrix
-  fp->splits_w = choose_splits(n, l, kc, cx.caps.num_cu);
-  fp->splits_g = choose_splits(l, l, kc, cx.caps.num_cu);
-  fp->splits_i = choose_splits(l, l, l, cx.caps.num_cu);
-  fp->splits_b = choose_splits(n, l, l, cx.caps.num_cu);
+  fp->splits_w = choose_splits(n, l, kc, caps.num_cu);
+  fp->splits_g = choose_splits(l, l, kc, caps.num_cu);
+  fp->splits_i = choose_splits(l, l, l, caps.num_cu);
+  fp->splits_b = choose_splits(n, l, l, caps.num_cu);
   Carver cv;
-  plan_sketch_part(cv, *fp, n, l, p->s);
+  plan_sketch_part(cv, *fp, A, p);
   fp->sketch_total = cv.off;
-  fp->Y = cv.take((size_t)m * l * 8);
+  fp->Y = cv.take((size_t)m * ls * 8);
+  const bool trunc = truncated(p);
+  fp->splits_y = trunc ? choose_splits(ls, ls, m, caps.num_cu) : 1;
+  fp->Gy = cv.take(trunc ? (size_t)ls * ls * 8 : 0);
+  fp->parts_y = cv.take(trunc ? gemm_f64_splitk_scratch(ls, ls, fp->splits_y) : 0);
+  fp->Rsel = cv.take(trunc ? (size_t)ls * l * 8 : 0);
+  fp->ysel = cv.take(trunc ? (size_t)l * 4 : 0);
+  fp->Yk = cv.take(trunc ? (size_t)m * l * 8 : 0);
   fp->slots = cv.take(std::max(gepp_workspace_bytes(m, l, fp->py), gepp_workspace_bytes(n, l, fp->pb)));
   fp->Lhat = cv.take((size_t)m * l * 8);
   fp->Uy = cv.take((size_t)l * l * 8);
@@ -165,7 +185,7 @@ rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_pa
   fp->csc = cv.take(A->layout == RLU_CSR ? csc_scratch_bytes(n, A->nnz) : 0);
   fp->pp = PrecPlan{};
   if (A->layout == RLU_DENSE_ROW_MAJOR && p->precision != RLU_PREC_F64 &&
-      !plan_precision(m, n, l, p->precision, cx.caps.num_cu, &fp->pp))
+      !plan_precision(m, n, l, p->precision, caps.num_cu, &fp->pp))
     return fail(RLU_ERR_INVALID_ARG, "unknown precision %d", p->precision);
   fp->prec = cv.take(fp->pp.total);
   const size_t k2 = second ? (size_t)p->k2 : 0, l2 = second ? (size_t)p->l2 : 0;
@@ -204,7 +224,7 @@ static rlu_status run_params(const FactorPlan &fp, const rlu_params *p, void *ws
 // They depend on nothing but the seed and the shape.
 static rlu_status run_params2(const FactorPlan &fp, const rlu_params *p, void *ws, hipStream_t st) {
   hipError_t e = launch_omega2_lists(fp.m, fp.l2, p->seed, at<int32_t>(ws, fp.o2start), at<uint32_t>(ws, fp.o2list),
-                                     at<uint32_t>(ws, fp.o2code), st);
+                                     at<uint32_t>(ws, fp.o2code), deterministic(p), st);
   if (e != hipSuccess) return hip_fail(e, "second projection lists");
   launch_srft_params(fp.l2, fp.k2, p->seed, nullptr, at<int32_t>(ws, fp.o2sel), at<double2>(ws, fp.o2twf),
                      at<double2>(ws, fp.o2twp), st, true);
@@ -213,23 +233,47 @@ static rlu_status run_params2(const FactorPlan &fp, const rlu_params *p, void *w
 }
 
 
-static rlu_status run_sketch(const rlu_ctx_impl &cx, const FactorPlan &fp, const rlu_matrix *A,
+static rlu_status run_sketch(const DevCaps &caps, const FactorPlan &fp, const rlu_matrix *A,
                              const rlu_params *p, double *Y, int64_t ldy, void *ws, rlu_info *info,
                              hipStream_t st) {
   hipError_t e;
-  if (A->layout == RLU_DENSE_ROW_MAJOR) {
+  const bool hadamard = (p->flags & RLU_FLAG_HADAMARD) != 0;
+  const bool wide = p->s > kLdsMaxS;
+  double *gctab = nullptr;
+  if (wide && !hadamard) {
+    gctab = at<double>(ws, fp.ctabg);
+    if ((e = launch_cos_table(p->s, at<double2>(ws, fp.twp), gctab, st)) != hipSuccess) return hip_fail(e, "cos table");
+  }
+  if (A->layout == RLU_DENSE_ROW_MAJOR && wide) {
+    // the row's s buckets do not fit in LDS: Y = A Omega^T with Omega^T explicit
+    double *OmT = at<double>(ws, fp.omt);
+    e = launch_explicit_projection(A->n, p->s, p->l, at<uint32_t>(ws, fp.code), at<int32_t>(ws, fp.sel), gctab,
+                                   hadamard, OmT, st);
+    if (e != hipSuccess) return hip_fail(e, "explicit projection");
+    GemmArgs g{};
+    g.M = A->m; g.N = p->l; g.K = A->n;
+    g.A = A->values; g.lda = A->ld; g.a_dtype = A->dtype; g.trans_a = false;
+    g.B = OmT; g.ldb = p->l;
+    g.C = Y; g.ldc = ldy; g.alpha = 1.0; g.beta = 0.0;
+    e = gemm_f64(g, st);
+  } else if (A->layout == RLU_DENSE_ROW_MAJOR && deterministic(p)) {
+    e = launch_sketch_ordered(A->m, A->n, A->values, A->dtype, A->ld, p->s, p->l, at<uint32_t>(ws, fp.code),
+                              at<int32_t>(ws, fp.sel), at<double2>(ws, fp.twf), at<double2>(ws, fp.twp),
+                              at<void>(ws, fp.ordt), Y, ldy, caps.num_cu, (p->flags & RLU_FLAG_HADAMARD) != 0,
+                              st);
+  } else if (A->layout == RLU_DENSE_ROW_MAJOR) {
     e = launch_sketch_dense(A->m, A->n, A->values, A->dtype, A->ld, p->s, p->l, at<uint32_t>(ws, fp.code),
                             at<int32_t>(ws, fp.sel), at<double2>(ws, fp.twf), at<double2>(ws, fp.twp),
-                            Y, ldy, at<uint32_t>(ws, fp.ctl) + 3, cx.caps.num_cu, (p->flags & RLU_FLAG_HADAMARD) != 0, st);
+                            Y, ldy, at<uint32_t>(ws, fp.ctl) + 3, caps.num_cu, (p->flags & RLU_FLAG_HADAMARD) != 0, st);
   } else {
     if (info) {
       e = launch_csr_check(A, (p->flags & RLU_FLAG_VALIDATE) != 0, info, st);
       if (e != hipSuccess) return hip_fail(e, "CSR check");
     }
     e = launch_sketch_csr(A->m, A->n, A->row_ptr, A->col_idx, (const double *)A->values, A->nnz, p->s, p->l,
-                          at<uint32_t>(ws, fp.code), at<int32_t>(ws, fp.sel), at<double2>(ws, fp.twf),
-                          at<double2>(ws, fp.twp), Y, ldy, info ? &info->bad_index : at<int32_t>(ws, fp.ctl) + 2,
-                          cx.caps.num_cu, (p->flags & RLU_FLAG_HADAMARD) != 0, st);
+                          at<uint32_t>(ws, fp.code), at<int32_t>(ws, fp.sel), at<double2>(ws, fp.twp),
+                          gctab, Y, ldy, info ? &info->bad_index : at<int32_t>(ws, fp.ctl) + 2,
+                          caps.num_cu, hadamard, st);
   }
   return e == hipSuccess ? RLU_OK : hip_fail(e, "sketch kernel");
 }
@@ -238,15 +282,15 @@ static rlu_status run_sketch(const rlu_ctx_impl &cx, const FactorPlan &fp, const
 // (S_2 P X)^T into Z0T, the transform down its columns as the row sketch of
 // Z0T (identity SEM, d_2 in the codes) into ZT, then Zs = Omega_2 P X
 // (k2 x ncols, ld ncols).
-static rlu_status omega2_apply(const rlu_ctx_impl &cx, const FactorPlan &fp, const void *X, int dtype, int64_t ldx,
+static rlu_status omega2_apply(const DevCaps &caps, const FactorPlan &fp, const void *X, int dtype, int64_t ldx,
                                int64_t ncols, const int32_t *perm, double *Z0T, double *ZT, double *Zs,
-                               uint32_t *row_counter, bool hadamard, void *ws, hipStream_t st) {
+                               uint32_t *row_counter, bool hadamard, bool ordered, void *ws, hipStream_t st) {
   hipError_t e = launch_omega2_gather(ncols, X, dtype, ldx, perm, at<int32_t>(ws, fp.o2start),
-                                      at<uint32_t>(ws, fp.o2list), fp.l2, Z0T, fp.l2, st);
+                                      at<uint32_t>(ws, fp.o2list), fp.l2, Z0T, fp.l2, ordered, st);
   if (e != hipSuccess) return hip_fail(e, "second projection: sparse embedding");
   e = launch_sketch_dense(ncols, fp.l2, Z0T, RLU_F64, fp.l2, fp.l2, fp.k2, at<uint32_t>(ws, fp.o2code),
                           at<int32_t>(ws, fp.o2sel), at<double2>(ws, fp.o2twf), at<double2>(ws, fp.o2twp), ZT, fp.k2,
-                          row_counter, cx.caps.num_cu, hadamard, st);
+                          row_counter, caps.num_cu, hadamard, st);
   if (e != hipSuccess) return hip_fail(e, "second projection: transform");
   if ((e = launch_transpose(ncols, fp.k2, ZT, fp.k2, Zs, ncols, st)) != hipSuccess)
     return hip_fail(e, "second projection: transpose");
@@ -318,9 +362,11 @@ void destroy_aux_streams(rlu_ctx_impl &cx) {
 }
 
 rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_params *p,
-                          const rlu_factors *out, void *ws, const FactorPlan &fp, hipStream_t st) {
+                          const rlu_factors *out, void *ws, const FactorPlan &fp, hipStream_t st,
+                          const ExecEnv *env) {
+  const DevCaps &caps = env ? env->caps : cx.caps;
   const int64_t m = A->m, n = A->n;
-  const int l = p->l;
+  const int l = fp.l;  // rank of the factors (k with RLU_FLAG_TRUNCATE); the sketch has fp.ls columns
   hipError_t e;
   StageMarks sm;
   if (p->flags & (RLU_FLAG_TIMING | RLU_FLAG_TIMING_CONTRACT)) {
@@ -329,8 +375,9 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     if (ts != RLU_OK) return ts;
   }
   AuxStream ax;
-  rlu_status rs = aux_for(cx, st, &ax);
-  if (rs != RLU_OK) return rs;
+  rlu_status rs = RLU_OK;
+  if (env) ax = env->ax;
+  else if ((rs = aux_for(cx, st, &ax)) != RLU_OK) return rs;
   sm.begin(RLU_STAGE_PARAMS, st);
   rlu_info *info = out->info;
   uint32_t *ctl = at<uint32_t>(ws, fp.ctl);
@@ -344,9 +391,29 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   sm.end(RLU_STAGE_PARAMS, st);
 
   double *Y = out->Y ? out->Y : at<double>(ws, fp.Y);
-  const int64_t ldy = out->Y ? out->ldy : l;
+  int64_t ldy = out->Y ? out->ldy : fp.ls;
   sm.begin(RLU_STAGE_SKETCH, st);
-  if ((rs = run_sketch(cx, fp, A, p, Y, ldy, ws, info, st)) != RLU_OK) return rs;
+  if ((rs = run_sketch(caps, fp, A, p, Y, ldy, ws, info, st)) != RLU_OK) return rs;
+  if (truncated(p)) {
+    // rank-k factors: k columns of Y by column pivoting (the first k pivots of
+    // Y's column-pivoted QR, as pivoted Cholesky of Y^T Y); steps 3-6 then run
+    // on those columns
+    double *Gy = at<double>(ws, fp.Gy);
+    GemmArgs g{};
+    g.M = fp.ls; g.N = fp.ls; g.K = m;
+    g.A = Y; g.lda = ldy; g.a_dtype = RLU_F64; g.trans_a = true;
+    g.B = Y; g.ldb = ldy;
+    g.C = Gy; g.ldc = fp.ls; g.alpha = 1.0; g.beta = 0.0;
+    if ((e = gemm_f64_splitk(g, fp.splits_y, at<double>(ws, fp.parts_y), st)) != hipSuccess)
+      return hip_fail(e, "Gram matrix of Y");
+    int32_t *ysel = out->ysel ? out->ysel : at<int32_t>(ws, fp.ysel);
+    if ((e = launch_colsel(fp.ls, l, Gy, at<double>(ws, fp.Rsel), ysel, info, st)) != hipSuccess)
+      return hip_fail(e, "column selection");
+    double *Yk = at<double>(ws, fp.Yk);
+    if ((e = launch_gather_cols(m, l, Y, ldy, ysel, Yk, st)) != hipSuccess) return hip_fail(e, "column gather");
+    Y = Yk;
+    ldy = l;
+  }
   sm.end(RLU_STAGE_SKETCH, st);
   if (second) {  // Omega_2's parameters on the auxiliary stream, beside step 3 (whose
                  // panels leave most CUs idle); the streaming sketch would share its CUs
@@ -360,7 +427,7 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   double *Lhat = at<double>(ws, fp.Lhat);
   double *Uy = out->Uy ? out->Uy : at<double>(ws, fp.Uy);
   sm.begin(RLU_STAGE_LU_Y, st);
-  const bool exclusive = (p->flags & RLU_FLAG_EXCLUSIVE) != 0;
+  const bool exclusive = (p->flags & RLU_FLAG_EXCLUSIVE) != 0 || (env && env->exclusive);
   e = launch_gepp(m, l, Y, ldy, Lhat, Uy, out->perm_r, out->ipiv_r, at<void>(ws, fp.slots), abort_flag, info,
                   0, fp.py, exclusive, st);
   if (e != hipSuccess) return hip_fail(e, "row-pivoted LU launch");
@@ -378,19 +445,26 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   // chain after G is latency-bound and runs on the auxiliary stream beside
   // Z's pass and W^T = Z^T M; B^T = W^T G^{-1} then ends both forms alike.
   const bool hadamard = (p->flags & RLU_FLAG_HADAMARD) != 0;
-  const bool overlap = second || A->layout == RLU_CSR || (double)m * (double)n * (double)l >= 1e11;
+  const bool det = deterministic(p);
+  const bool overlap = (!env || env->overlap) &&
+                       (second || A->layout == RLU_CSR || (double)m * (double)n * (double)l >= 1e11);
   hipStream_t gs = overlap ? ax.aux : st;
-  hipStream_t gram_st = second ? st : gs;  // stream of the Gram stage
+  // The Gram matrix first, on the caller's stream, with the second projection
+  // (see above) and with the BF16 form, whose contraction is short enough that
+  // a Gram product starved beside it would put the Cholesky chain on the
+  // critical path; otherwise it runs beside the contraction as well.
+  const bool gram_first = second || (overlap && p->precision == RLU_PREC_BF16_REFINED);
+  hipStream_t gram_st = gram_first ? st : gs;  // stream of the Gram stage
   double *Ms = at<double>(ws, fp.Ms);
   if (second && (e = hipStreamWaitEvent(st, ax.join, 0)) != hipSuccess) return hip_fail(e, "join");  // parameters
-  if (overlap && !second) {
+  if (overlap && !gram_first) {
     if ((e = hipEventRecord(ax.fork, st)) != hipSuccess || (e = hipStreamWaitEvent(ax.aux, ax.fork, 0)) != hipSuccess)
       return hip_fail(e, "fork");
   }
   sm.begin(RLU_STAGE_GRAM, gram_st);
   if (second) {  // M = Omega_2 L_y = Omega_2 P Lhat
-    rs = omega2_apply(cx, fp, Lhat, RLU_F64, l, l, out->perm_r, at<double>(ws, fp.M0T), at<double>(ws, fp.MT), Ms,
-                      ctl + 4, hadamard, ws, gram_st);
+    rs = omega2_apply(caps, fp, Lhat, RLU_F64, l, l, out->perm_r, at<double>(ws, fp.M0T), at<double>(ws, fp.MT), Ms,
+                      ctl + 4, hadamard, det, ws, gram_st);
     if (rs != RLU_OK) return rs;
   }
   {
@@ -403,7 +477,7 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     if (e != hipSuccess) return hip_fail(e, "Gram matrix");
   }
   sm.end(RLU_STAGE_GRAM, gram_st);
-  if (second) {
+  if (overlap && gram_first) {
     if ((e = hipEventRecord(ax.fork, st)) != hipSuccess || (e = hipStreamWaitEvent(ax.aux, ax.fork, 0)) != hipSuccess)
       return hip_fail(e, "fork");
   }
@@ -429,24 +503,24 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     // as a CSC copy of A, with Omega_2's codes by row of A
     CscView cs;
     if ((e = build_csc(m, n, A->row_ptr, A->col_idx, (const double *)A->values, A->nnz, at<void>(ws, fp.csc),
-                       cx.caps.num_cu, st, &cs)) != hipSuccess)
+                       caps.num_cu, det, st, &cs)) != hipSuccess)
       return hip_fail(e, "CSC copy");
     uint32_t *rowcode = at<uint32_t>(ws, fp.o2rowcode);
     if ((e = launch_omega2_rowcodes(m, fp.l2, p->seed, out->perm_r, rowcode, st)) != hipSuccess)
       return hip_fail(e, "second projection codes");
     e = launch_sketch_csr(n, m, cs.colptr, cs.crow, cs.cval, A->nnz, fp.l2, fp.k2, rowcode, at<int32_t>(ws, fp.o2sel),
-                          at<double2>(ws, fp.o2twf), at<double2>(ws, fp.o2twp), at<double>(ws, fp.ZT), fp.k2,
-                          reinterpret_cast<int32_t *>(ctl + 6), cx.caps.num_cu, hadamard, st);
+                          at<double2>(ws, fp.o2twp), nullptr, at<double>(ws, fp.ZT), fp.k2,
+                          reinterpret_cast<int32_t *>(ctl + 6), caps.num_cu, hadamard, st);
     if (e != hipSuccess) return hip_fail(e, "second projection: sparse sketch");
     if ((e = launch_transpose(n, fp.k2, at<double>(ws, fp.ZT), fp.k2, at<double>(ws, fp.Zs), n, st)) != hipSuccess)
       return hip_fail(e, "second projection: transpose");
   } else if (second) {  // Z = Omega_2 P A
-    rs = omega2_apply(cx, fp, A->values, A->dtype, A->ld, n, out->perm_r, at<double>(ws, fp.Z0T),
-                      at<double>(ws, fp.ZT), at<double>(ws, fp.Zs), ctl + 5, hadamard, ws, st);
+    rs = omega2_apply(caps, fp, A->values, A->dtype, A->ld, n, out->perm_r, at<double>(ws, fp.Z0T),
+                      at<double>(ws, fp.ZT), at<double>(ws, fp.Zs), ctl + 5, hadamard, det, ws, st);
     if (rs != RLU_OK) return rs;
   } else if (A->layout == RLU_CSR) {
     e = contraction_csr(m, n, l, A->row_ptr, A->col_idx, (const double *)A->values, A->nnz, Lhat, Wt,
-                        at<void>(ws, fp.csc), cx.caps.num_cu, st);
+                        at<void>(ws, fp.csc), caps.num_cu, det, st);
     if (e != hipSuccess) return hip_fail(e, "sparse contraction");
   } else if (p->precision == RLU_PREC_F64) {
     GemmArgs g{};
@@ -561,7 +635,7 @@ static rlu_status sketch_call(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_p
   if (ldy < p->l) return fail(RLU_ERR_INVALID_ARG, "ldy (%lld) < l (%d)", (long long)ldy, p->l);
   FactorPlan fp;
   Carver cv;
-  plan_sketch_part(cv, fp, A->n, p->l, p->s);
+  plan_sketch_part(cv, fp, A, p);
   fp.n = A->n;
   fp.m = A->m;
   if (noalloc && cv.off > ws_bytes)
@@ -575,7 +649,7 @@ static rlu_status sketch_call(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_p
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if ((e = launch_fill_u32(at<uint32_t>(ws, fp.ctl), 0u, kCtlWords, s)) != hipSuccess) return hip_fail(e, "fill");
   if ((st = run_params(fp, p, ws, s)) != RLU_OK) return st;
-  return run_sketch(cx, fp, A, p, Y, ldy, ws, nullptr, s);
+  return run_sketch(cx.caps, fp, A, p, Y, ldy, ws, nullptr, s);
 }
 
 }  // namespace rlu
@@ -636,7 +710,7 @@ rlu_status rlu_workspace_size(rlu_ctx *ctx, const rlu_matrix *A, const rlu_param
   if (st != RLU_OK) return st;
   if ((st = validate_params(A, p)) != RLU_OK) return st;
   FactorPlan fp;
-  if ((st = plan_factor(*reinterpret_cast<rlu_ctx_impl *>(ctx), A, p, &fp)) != RLU_OK) return st;
+  if ((st = plan_factor(reinterpret_cast<rlu_ctx_impl *>(ctx)->caps, A, p, &fp)) != RLU_OK) return st;
   *bytes = fp.total;
   return RLU_OK;
 }
@@ -676,12 +750,12 @@ rlu_status rlu_factor(rlu_ctx *ctx, const rlu_matrix *A, const rlu_params *p, co
   if ((st = validate_params(A, p)) != RLU_OK) return st;
   if ((st = validate_factors(A, p, out)) != RLU_OK) return st;
   FactorPlan fp;
-  if ((st = plan_factor(cx, A, p, &fp)) != RLU_OK) return st;
+  if ((st = plan_factor(cx.caps, A, p, &fp)) != RLU_OK) return st;
   if (!ws || ws_bytes < fp.total || (reinterpret_cast<uintptr_t>(ws) & 255))
     return fail(RLU_ERR_NO_MEMORY, "workspace must be 256-byte aligned and hold %zu bytes", fp.total);
   hipError_t e = hipSetDevice(cx.caps.device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  return factor_enqueue(cx, A, p, out, ws, fp, reinterpret_cast<hipStream_t>(stream));
+  return factor_enqueue(cx, A, p, out, ws, fp, reinterpret_cast<hipStream_t>(stream), nullptr);
 }
 
 rlu_status rlu_stage_times(rlu_ctx *ctx, float *ms, int *calls) {

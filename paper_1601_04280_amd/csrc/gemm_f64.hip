@@ -487,6 +487,10 @@ static hipError_t launch(const GemmArgs &g, int splits, int64_t Kc, double *part
     }
     return dispatch_shape<double, double, true, false>(sh, grid, k, st);
   }
+  if (g.a_dtype == RLU_F32) {  // FP32 storage, widened exactly (the explicit projection's A)
+    if (g.gather) return hipErrorInvalidValue;
+    return dispatch_shape<double, float, false, false>(sh, grid, k, st);
+  }
   if (g.a_dtype != RLU_F64) return hipErrorInvalidValue;
   if (g.gather) return dispatch_shape<double, double, false, true>(sh, grid, k, st);
   return dispatch_shape<double, double, false, false>(sh, grid, k, st);

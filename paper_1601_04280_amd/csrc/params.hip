@@ -89,7 +89,7 @@ void launch_sem_codes(int64_t n, int s, uint64_t seed, uint32_t *code, int32_t *
 void launch_srft_params(int s, int l, uint64_t seed, int8_t *d, int32_t *sel, double2 *twf,
                         double2 *twp, hipStream_t st, bool second) {
   const int blocks = std::max(1, std::min(64, (s + 255) / 256));
-  const size_t lds = sel ? (size_t)s * sizeof(int32_t) : 0;
+  const size_t lds = sel ? (size_t)std::max(1, l) * sizeof(int32_t) : 0;  // the l swap targets
   hipLaunchKernelGGL(k_srft_params, dim3(blocks), dim3(256), lds, st, s, l,
                      stream_key(seed, second ? kStreamSigns2 : kStreamSigns),
                      stream_key(seed, second ? kStreamSelect2 : kStreamSelect), d, sel, twf, twp);

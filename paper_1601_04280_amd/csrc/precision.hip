@@ -281,6 +281,136 @@ __global__ __launch_bounds__(256) void k_bf16_tn(Bf16Tn p) {
       }
 }
 
+// ---------------------------------------------------------------------------
+// Wide form of the same product for 128 < N <= 576 (N = l): one block spans
+// all N columns, so X (A, or R^T) is read from memory once instead of once
+// per 128-column tile; only Lb^T, the small operand, is read again by every
+// row tile.  K is split into `splits` ranges laid out so that each XCD works
+// on one range, whose slice of Lb^T then stays in that XCD's L2.  Eight waves
+// in a 2 x 4 grid, wave tile 64 x (16 WN), block tile 128 x (64 WN); K
+// advances 32 per stage through a double-buffered LDS tile, the next stage's
+// loads in flight during the current stage's MFMAs (v_mfma_f32_16x16x32_bf16).
+// FP32 partial sums per K range go to `parts` (summed in FP64 afterwards, in
+// a fixed order) or, with one range, straight to C.
+// ---------------------------------------------------------------------------
+template <typename TX, bool XT, int WN>
+__global__ __launch_bounds__(512) void k_bf16_tn_wide(Bf16Tn p) {
+  constexpr int BM = 128, BN = 64 * WN, BK = 32, LS = BK + 8;  // 80-byte rows
+  constexpr int QL = (BN * BK / 8 + 511) / 512;                 // 16-byte chunks of Lb^T per thread
+  __shared__ __attribute__((aligned(16))) uint16_t Xs[2][BM * LS];
+  __shared__ __attribute__((aligned(16))) uint16_t Ls[2][BN * LS];
+  const int64_t t = xcd_tile(p.per_xcd);
+  if (t >= p.tiles) return;
+  const int tm = (int)(t % p.ntm);
+  const int z = (int)(t / p.ntm);  // K range: consecutive tiles (one XCD) share it
+  const int64_t m0 = (int64_t)tm * BM;
+  const int64_t kb = (int64_t)z * p.Kc, ke = min(p.K, kb + p.Kc);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int xc = tid & 127, xk = tid >> 7;  // transposing loader: column xc, k rows 8 xk .. 8 xk + 7
+
+  TX rx[XT ? 1 : 8];
+  u32x4 rxq;
+  u32x4 rlq[QL];
+  auto load = [&](int64_t k0) {
+    if constexpr (XT) {
+      const uint16_t *Xb = reinterpret_cast<const uint16_t *>(p.X);
+      const int r = tid >> 2, kc = tid & 3;
+      const int64_t row = m0 + r < p.M ? m0 + r : m0;
+      rxq = *reinterpret_cast<const u32x4 *>(Xb + row * p.ldx + k0 + kc * 8);
+    } else {
+      const TX *X = reinterpret_cast<const TX *>(p.X);
+      const int64_t col = m0 + xc;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t k = k0 + xk * 8 + e;
+        const bool ok = k < ke && col < p.M;
+        rx[e] = X[(ok ? k : kb) * p.ldx + (ok ? col : m0)];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < QL; ++q) {
+      const int e = tid + 512 * q;
+      const int r = min(e >> 2, p.ntn - 1), kc = e & 3;  // ntn: rows of Lb^T available
+      rlq[q] = *reinterpret_cast<const u32x4 *>(p.LbT + (int64_t)r * p.ldl + k0 + kc * 8);
+    }
+  };
+  auto store = [&](int buf, int64_t k0) {
+    const u32x4 zero = {0u, 0u, 0u, 0u};
+    if constexpr (XT) {
+      const int r = tid >> 2, kc = tid & 3;
+      *reinterpret_cast<u32x4 *>(&Xs[buf][r * LS + kc * 8]) = m0 + r < p.M ? rxq : zero;
+    } else {
+      const bool cok = m0 + xc < p.M;
+      TX v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (cok && k0 + xk * 8 + e < ke) ? rx[e] : (TX)0;
+      u32x4 w;
+      w.x = pack_bf16(v[0], v[1]);
+      w.y = pack_bf16(v[2], v[3]);
+      w.z = pack_bf16(v[4], v[5]);
+      w.w = pack_bf16(v[6], v[7]);
+      *reinterpret_cast<u32x4 *>(&Xs[buf][xc * LS + xk * 8]) = w;
+    }
+#pragma unroll
+    for (int q = 0; q < QL; ++q) {
+      const int e = tid + 512 * q;
+      if (e < BN * BK / 8) {
+        const int r = e >> 2, kc = e & 3;
+        *reinterpret_cast<u32x4 *>(&Ls[buf][r * LS + kc * 8]) = r < p.ntn ? rlq[q] : zero;
+      }
+    }
+  };
+
+  f32x4 acc[4][WN];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  int buf = 0;
+  if (kb < ke) {
+    load(kb);
+    store(0, kb);
+    __syncthreads();
+  }
+  const int ko = 8 * (lane >> 4);
+  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+    const bool more = k0 + BK < ke;
+    if (more) load(k0 + BK);
+    bf16x8 a[4], b[WN];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      a[i] = *reinterpret_cast<const bf16x8 *>(&Xs[buf][(wm * 64 + i * 16 + (lane & 15)) * LS + ko]);
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+      b[j] = *reinterpret_cast<const bf16x8 *>(&Ls[buf][(wn * 16 * WN + j * 16 + (lane & 15)) * LS + ko]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    if (more) {
+      store(buf ^ 1, k0 + BK);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + v;
+        const int64_t col = wn * 16 * WN + j * 16 + (lane & 15);
+        if (row < p.M && col < p.N) {
+          if (p.parts) p.parts[(int64_t)z * p.M * p.N + row * p.N + col] = acc[i][j][v];
+          else p.C[row * p.ldc + col] = (double)acc[i][j][v];
+        }
+      }
+}
+
 __global__ void k_sum_parts(int64_t M, int64_t N, int splits, const float *__restrict__ parts, double *__restrict__ C,
                             int64_t ldc) {
   const int64_t total = M * N;
@@ -301,6 +431,8 @@ __global__ void k_sum_parts(int64_t M, int64_t N, int splits, const float *__res
 // (32 WM) x (32 WN), K advancing 32 at a time through a double-buffered LDS
 // tile.
 // ---------------------------------------------------------------------------
+constexpr int kResidSub = 8;  // column tiles of one sub-band (their X operands: 2.2 MB at K = 544)
+
 struct Bf16Resid {
   int64_t M, N, Mp;
   int K;
@@ -310,6 +442,7 @@ struct Bf16Resid {
   uint16_t *RT;
   int64_t ldr;
   int ntn;
+  int64_t ntm;
   int64_t tiles, per_xcd;
 };
 
@@ -320,10 +453,20 @@ __global__ __launch_bounds__(256) void k_bf16_resid(Bf16Resid p) {
   static_assert(QM >= 1 && QN >= 1, "tile too small");
   __shared__ __attribute__((aligned(16))) uint16_t Lhs[2][BM * LS], Lls[2][BM * LS], Xhs[2][BN * LS],
       Xls[2][BN * LS];
-  const int64_t t = xcd_tile(p.per_xcd);
-  if (t >= p.tiles) return;
-  const int tn = (int)(t % p.ntn);
-  const int64_t tm = t / p.ntn;
+  // Column tiles by XCD: XCD x owns a band of nb = ceil(ntn / 8) column
+  // tiles and walks every row tile over sub-bands of kResidSub of them, so
+  // the X operands of a sub-band stay in that XCD's L2 while the row tiles'
+  // L operands stream through it (hardware block ids go to the XCDs in turn).
+  const int xcd = (int)(blockIdx.x & 7);
+  const int64_t j = blockIdx.x >> 3;
+  const int nb = (int)ceil_div(p.ntn, 8);
+  const int64_t per_sub = p.ntm * kResidSub;
+  const int sub = (int)(j / per_sub);
+  const int64_t rem = j - (int64_t)sub * per_sub;
+  const int64_t tm = rem / kResidSub;
+  const int tl = sub * kResidSub + (int)(rem % kResidSub);  // column tile within the band
+  const int tn = xcd * nb + tl;
+  if (tl >= nb || tn >= p.ntn || tm >= p.ntm) return;
   const int64_t m0 = tm * BM, n0 = (int64_t)tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -447,7 +590,20 @@ static T *at(void *base, size_t off) { return reinterpret_cast<T *>(reinterpret_
 constexpr int kRowPad = 128;  // rows of LbT padded to the widest N tile
 constexpr int kKPad = 64;     // K padding of the K-contiguous operands
 
+constexpr int kWideMaxN = 576;  // the wide product's widest block (WN = 9)
+constexpr int kWideSplits = 8;  // one K range per XCD
+
 static void bf16_tn_shape(int64_t M, int64_t N, int64_t K, int num_cu, int *wm, int *wn, int *splits, int64_t *Kc) {
+  if (N > 128 && N <= kWideMaxN) {  // the wide form: wn = WN (block tile 64 WN columns), wm = 0 marks it
+    *wm = 0;
+    *wn = (int)ceil_div(N, 64);
+    int64_t s = std::max<int64_t>(1, std::min<int64_t>(kWideSplits, K / 1024));
+    int64_t kc = ceil_div(std::max<int64_t>(K, 1), s);
+    kc = ceil_div(kc, kKPad) * kKPad;
+    *Kc = kc;
+    *splits = (int)ceil_div(std::max<int64_t>(K, 1), kc);
+    return;
+  }
   *wm = M > 64 ? 4 : 2;
   *wn = N > 64 ? 4 : 2;
   const int64_t tiles = ceil_div(M, 32 * *wm) * ceil_div(N, 32 * *wn);
@@ -493,6 +649,20 @@ bool plan_precision(int64_t m, int64_t n, int l, int precision, int num_cu, Prec
 static unsigned ew_blocks(int64_t total) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(8192, ceil_div(total, 256))); }
 
 template <typename TX, bool XT>
+static hipError_t launch_tn_wide(const Bf16Tn &k, int wn, unsigned grid, hipStream_t st) {
+  switch (wn) {
+#define RLU_WIDE(W)                                                                          \
+  case W:                                                                                    \
+    hipLaunchKernelGGL((k_bf16_tn_wide<TX, XT, W>), dim3(grid), dim3(512), 0, st, k);         \
+    break;
+    RLU_WIDE(3) RLU_WIDE(4) RLU_WIDE(5) RLU_WIDE(6) RLU_WIDE(7) RLU_WIDE(8) RLU_WIDE(9)
+#undef RLU_WIDE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename TX, bool XT>
 static hipError_t launch_tn_t(const Bf16Tn &k, int wm, int wn, unsigned grid, hipStream_t st) {
   if (wm == 4 && wn == 4) hipLaunchKernelGGL((k_bf16_tn<TX, XT, 4, 4>), dim3(grid), dim3(256), 0, st, k);
   else if (wm == 4 && wn == 2) hipLaunchKernelGGL((k_bf16_tn<TX, XT, 4, 2>), dim3(grid), dim3(256), 0, st, k);
@@ -506,9 +676,31 @@ static hipError_t launch_tn_t(const Bf16Tn &k, int wm, int wn, unsigned grid, hi
 // FP32 / FP64 (xt = false) or X^T: M x K_p BF16 (ldx) (xt = true).  parts must
 // hold splits x M x N floats when splits > 1.
 static hipError_t bf16_tn(int64_t M, int64_t N, int64_t K, const void *X, int x_dtype, bool xt, int64_t ldx,
-                          const uint16_t *LbT, int64_t ldl, double *C, int64_t ldc, int wm, int wn, int splits,
-                          int64_t Kc, float *parts, hipStream_t st) {
+                          const uint16_t *LbT, int64_t ldl, int64_t lb_rows, double *C, int64_t ldc, int wm, int wn,
+                          int splits, int64_t Kc, float *parts, hipStream_t st) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  if (wm == 0) {  // wide form: one block spans all N columns, K ranges by XCD
+    Bf16Tn k{};
+    k.M = M; k.N = N; k.K = K;
+    k.X = X; k.ldx = ldx; k.LbT = LbT; k.ldl = ldl;
+    k.C = C; k.ldc = ldc;
+    k.parts = splits > 1 ? parts : nullptr;
+    k.Kc = splits > 1 ? Kc : ceil_div(std::max<int64_t>(K, 1), kKPad) * kKPad;
+    k.ntm = (int)ceil_div(M, 128);
+    k.ntn = (int)lb_rows;  // rows of Lb^T that may be read
+    const int used = splits > 1 ? (int)ceil_div(K, Kc) : 1;
+    k.tiles = (int64_t)k.ntm * used;
+    const unsigned grid = xcd_grid(k.tiles, &k.per_xcd);
+    hipError_t e;
+    if (xt) e = launch_tn_wide<uint16_t, true>(k, wn, grid, st);
+    else if (x_dtype == RLU_F32) e = launch_tn_wide<float, false>(k, wn, grid, st);
+    else if (x_dtype == RLU_F64) e = launch_tn_wide<double, false>(k, wn, grid, st);
+    else return hipErrorInvalidValue;
+    if (e != hipSuccess || used <= 1) return e;
+    hipLaunchKernelGGL(k_sum_parts, dim3(ew_blocks(M * N)), dim3(256), 0, st, M, N, used, (const float *)parts, C,
+                       ldc);
+    return hipGetLastError();
+  }
   Bf16Tn k{};
   k.M = M; k.N = N; k.K = K;
   k.X = X; k.ldx = ldx; k.LbT = LbT; k.ldl = ldl;
@@ -541,8 +733,10 @@ static hipError_t bf16_resid(int64_t M, int64_t N, int64_t Mp, int K, const void
   k.Lh = Lh; k.Ll = Ll; k.Xh = Xh; k.Xl = Xl;
   k.RT = RT; k.ldr = ldr;
   k.ntn = (int)ceil_div(N, 32 * w);
-  k.tiles = ceil_div(Mp, 32 * w) * k.ntn;  // row tiles cover the zero columns of R^T too
-  const unsigned grid = xcd_grid(k.tiles, &k.per_xcd);
+  k.ntm = ceil_div(Mp, 32 * w);  // row tiles cover the zero columns of R^T too
+  k.tiles = k.ntm * k.ntn;
+  const int64_t nb = ceil_div(k.ntn, 8), subs = ceil_div(nb, kResidSub);
+  const unsigned grid = (unsigned)(8 * subs * k.ntm * kResidSub);
   if (a_dtype == RLU_F32) {
     if (w == 4) hipLaunchKernelGGL((k_bf16_resid<float, 4, 4>), dim3(grid), dim3(256), 0, st, k);
     else hipLaunchKernelGGL((k_bf16_resid<float, 2, 2>), dim3(grid), dim3(256), 0, st, k);
@@ -580,8 +774,8 @@ hipError_t precision_contract(const PrecPlan &pp, const rlu_matrix *A, const dou
   hipLaunchKernelGGL(k_transpose_bf16, dim3((unsigned)(pp.mp / 64), (unsigned)(pp.np_rows / 64)), dim3(256), 0, st, m,
                      pp.lp, (const uint16_t *)Lh, (int64_t)pp.lp, LhT, pp.mp);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  return bf16_tn(n, l, m, A->values, A->dtype, false, A->ld, LhT, pp.mp, Wt, l, pp.wm, pp.wn, pp.splits, pp.Kc,
-                 at<float>(scratch, pp.parts), st);
+  return bf16_tn(n, l, m, A->values, A->dtype, false, A->ld, LhT, pp.mp, pp.np_rows, Wt, l, pp.wm, pp.wn, pp.splits,
+                 pp.Kc, at<float>(scratch, pp.parts), st);
 }
 
 hipError_t precision_refine(const PrecPlan &pp, const rlu_matrix *A, int l, double *Wt, const double *Ginv,
@@ -607,7 +801,7 @@ hipError_t precision_refine(const PrecPlan &pp, const rlu_matrix *A, int l, doub
   if ((e = bf16_resid(m, n, pp.mp, pp.lp, A->values, A->dtype, A->ld, Lh, Ll, Xh, Xl, RT, pp.mp, st)) != hipSuccess)
     return e;
   // dW^T = bf16(R)^T bf16(Lhat), over W0^T
-  if ((e = bf16_tn(n, l, m, RT, 0, true, pp.mp, LhT, pp.mp, Wt, l, pp.wm, pp.wn, pp.splits, pp.Kc,
+  if ((e = bf16_tn(n, l, m, RT, 0, true, pp.mp, LhT, pp.mp, pp.np_rows, Wt, l, pp.wm, pp.wn, pp.splits, pp.Kc,
                    at<float>(scratch, pp.parts), st)) != hipSuccess)
     return e;
   GemmArgs g{};  // B^T = X0^T + dW^T G^{-1}

@@ -22,7 +22,19 @@ inline int ilog2_exact(int64_t v) {
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-constexpr int kMaxS = 8192;            // LDS-resident transform: 16 s bytes per block
+constexpr int kMaxS = 65536;           // SEM width s: the codes keep 16 bits of bucket
+constexpr int kLdsMaxS = 8192;         // LDS-resident transform: 16 s bytes per block; wider
+                                       // s takes the explicit-projection route
+constexpr int kMaxL2 = 8192;           // SEM width of Omega_2 (its transform is LDS-resident)
+constexpr int kMaxL = 1024;            // sketch width l: the Cholesky panel (l x 17 doubles) and the
+                                       // triangular inverse's column (l doubles) live in LDS, the CSR
+                                       // kernels hold 16 outputs per lane, column selection one
+                                       // column per thread
+// Column selection of the truncated form: ysel[0..k) from G = Y^T Y (l x l);
+// Rt: l x k doubles of scratch
+hipError_t launch_colsel(int l, int k, const double *G, double *Rt, int32_t *ysel, rlu_info *info, hipStream_t st);
+hipError_t launch_gather_cols(int64_t m, int k, const double *Y, int64_t ldy, const int32_t *ysel, double *Yk,
+                              hipStream_t st);
 constexpr int kSketchThreads = 256;
 
 // ---- parameters -----------------------------------------------------------
@@ -33,18 +45,20 @@ void launch_srft_params(int s, int l, uint64_t seed, int8_t *d, int32_t *sel, do
                         double2 *twp, hipStream_t st, bool second = false);
 // Omega_2 (Algorithm 1 step 4): bucket lists of its SEM over m positions
 // (start: l2 + 1 offsets into list; list: position | sign bit 31) and the
-// transform step's codes (code2: l2 entries)
+// transform step's codes (code2: l2 entries); `ordered`: each list sorted by
+// position
 hipError_t launch_omega2_lists(int64_t m, int l2, uint64_t seed, int32_t *start, uint32_t *list,
-                               uint32_t *code2, hipStream_t st);
+                               uint32_t *code2, bool ordered, hipStream_t st);
 // Codes of Omega_2's SEM by row of A: code_row[perm[p]] = h_2(p) with bit 31
 // set when sgn_2(p) d_2(h_2(p)) = -1 (p < m, the pivoted position)
 hipError_t launch_omega2_rowcodes(int64_t m, int l2, uint64_t seed, const int32_t *perm, uint32_t *code_row,
                                   hipStream_t st);
 // Z0T (ncols x l2, ldz) = (S_2 P X)^T for X with m rows (row i of P X is
-// row perm[i] of X); dtype RLU_F64 or RLU_F32
+// row perm[i] of X); dtype RLU_F64 or RLU_F32.  `ordered` (with ordered
+// lists): every bucket summed in list order, the same on every run
 hipError_t launch_omega2_gather(int64_t ncols, const void *X, int dtype, int64_t ldx, const int32_t *perm,
                                 const int32_t *start, const uint32_t *list, int l2, double *Z0T, int64_t ldz,
-                                hipStream_t st);
+                                bool ordered, hipStream_t st);
 
 // ---- sketch -----------------------------------------------------------------
 struct SketchPlan {
@@ -57,25 +71,40 @@ hipError_t launch_sketch_dense(int64_t m, int64_t n, const void *A, int dtype, i
                                int l, const uint32_t *code, const int32_t *sel,
                                const double2 *twf, const double2 *twp, double *Y, int64_t ldy,
                                uint32_t *row_counter, int num_cu, bool hadamard, hipStream_t st);
+// gctab: for s > kLdsMaxS, the cos table in global memory (launch_cos_table),
+// else nullptr (the kernel builds it in LDS from twp)
 hipError_t launch_sketch_csr(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t *col,
                              const double *val, int64_t nnz, int s, int l, const uint32_t *code,
-                             const int32_t *sel, const double2 *twf, const double2 *twp, double *Y,
+                             const int32_t *sel, const double2 *twp, const double *gctab, double *Y,
                              int64_t ldy, int32_t *bad_index, int num_cu, bool hadamard, hipStream_t st);
 hipError_t launch_csr_check(const rlu_matrix *A, int validate_rows, rlu_info *info, hipStream_t st);
 size_t csc_scratch_bytes(int64_t n, int64_t nnz);
 // CSC copy of CSR A in `scratch` (csc_scratch_bytes): column pointers (n + 1),
-// row indices and values; entries of a column in no particular order
+// row indices and values; entries of a column in no particular order, or by
+// ascending row when `sorted`
 struct CscView {
   const int32_t *colptr;
   const int32_t *crow;
   const double *cval;
 };
 hipError_t build_csc(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
-                     int64_t nnz, void *scratch, int num_cu, hipStream_t st, CscView *out);
+                     int64_t nnz, void *scratch, int num_cu, bool sorted, hipStream_t st, CscView *out);
 // W^T (n x l) = A^T Lhat for CSR A, through a CSC copy built in `scratch`
 hipError_t contraction_csr(int64_t m, int64_t n, int l, const int32_t *row_ptr, const int32_t *col,
                            const double *val, int64_t nnz, const double *Lhat, double *Wt, void *scratch,
-                           int num_cu, hipStream_t st);
+                           int num_cu, bool sorted, hipStream_t st);
+// Explicit projection for s > kLdsMaxS: OmT (n x l, row major) with
+// OmT[j, q] = (folded sign of j) T[h(j), sel[q]], then Y = A OmT on the GEMM.
+// ctab: cos(2 pi k / s) for k < s (launch_cos_table), unused by the Hadamard form.
+hipError_t launch_cos_table(int s, const double2 *twp, double *ctab, hipStream_t st);
+hipError_t launch_explicit_projection(int64_t n, int s, int l, const uint32_t *code, const int32_t *sel,
+                                      const double *ctab, bool hadamard, double *OmT, hipStream_t st);
+// Bucket-ordered dense sketch (RLU_FLAG_DETERMINISTIC): every bucket sum in
+// ascending column order.  `tables`: ordered_tables_bytes(n, s) of workspace.
+size_t ordered_tables_bytes(int64_t n, int s);
+hipError_t launch_sketch_ordered(int64_t m, int64_t n, const void *A, int dtype, int64_t lda, int s, int l,
+                                 const uint32_t *code, const int32_t *sel, const double2 *twf, const double2 *twp,
+                                 void *tables, double *Y, int64_t ldy, int num_cu, bool hadamard, hipStream_t st);
 
 // ---- tall pivoted LU (cooperative) ---------------------------------------------
 struct GeppPlan {
@@ -213,7 +242,12 @@ struct FactorPlan {
   int k2 = 0, l2 = 0;  // second projection (k2 > 0), else the exact product
   // offsets (bytes) into the workspace
   size_t ctl, code, sel, twf, twp, Y, slots, csc, Lhat, Uy, Wt, parts, parts_g, Gm, Linv, Dinv, Ginv, Bt,
-      Lph, Up, Lt, prec, gaps;
+      Lph, Up, Lt, prec, gaps, ordt, ctabg, omt;
+  // truncated form: Y^T Y and its split partials, R of the selection, the
+  // selection (when the caller passes none) and the k chosen columns of Y
+  int ls = 0;        // sketch width (p->l); l above is the factors' rank
+  int splits_y = 1;
+  size_t Gy, parts_y, Rsel, ysel, Yk;
   // second projection: bucket lists and transform parameters of Omega_2,
   // (S_2 P A)^T, (Omega_2 P A)^T, Z = Omega_2 P A, and the same three for L_y
   size_t o2start, o2list, o2code, o2sel, o2twf, o2twp, Z0T, ZT, Zs, M0T, MT, Ms;
@@ -221,9 +255,21 @@ struct FactorPlan {
   size_t total;
   size_t sketch_total;
 };
-rlu_status plan_factor(const rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_params *p, FactorPlan *fp);
-// Enqueue every stage of one decomposition on `st` (arguments validated).
+rlu_status plan_factor(const DevCaps &caps, const rlu_matrix *A, const rlu_params *p, FactorPlan *fp);
+// Where one decomposition runs when it is not the context's own call: the
+// compute units it may use (num_cu of them, planned with these caps), its
+// auxiliary stream, whether its LU panels may be ordinary launches (every
+// block resident because nothing else runs on those compute units), and
+// whether stages may overlap on the auxiliary stream.
+struct ExecEnv {
+  DevCaps caps;
+  AuxStream ax;
+  bool exclusive = false;
+  bool overlap = true;
+};
+// Enqueue every stage of one decomposition on `st` (arguments validated);
+// env == nullptr: the context's device, caps and per-stream auxiliary stream.
 rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_params *p, const rlu_factors *out,
-                          void *ws, const FactorPlan &fp, hipStream_t st);
+                          void *ws, const FactorPlan &fp, hipStream_t st, const ExecEnv *env);
 
 }  // namespace rlu

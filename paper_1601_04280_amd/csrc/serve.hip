@@ -1,17 +1,30 @@
 // Serving: continuous batching of independent decompositions.
 //
 // rlu_serve_start allocates one HBM pool and `max_inflight` slots (a HIP
-// stream of default priority and a completion event each).  rlu_submit
-// validates and plans a request and queues it.  A worker thread admits
-// queued requests whenever a slot is free and the pool has room for the
-// request's workspace (serve_policy.h: first fit, oldest first, younger ones
-// may pass a head that does not fit a bounded number of times), enqueues the
-// request's whole stage sequence on the slot's stream, and retires it when the
-// slot's event completes, returning its workspace to the pool.  Requests of
-// different shapes therefore run concurrently on the device, and a request
-// that arrives while others are running starts as soon as memory and a slot
-// free up.  Sketches and intermediate factors live in the pool, outputs in
-// the caller's device buffers.  rlu_poll retires finished tickets.
+// stream of default priority, an auxiliary stream and a completion event
+// each).  rlu_submit validates and plans a request and queues it.  A worker
+// thread admits queued requests whenever a slot is free and the pool has room
+// for the request's workspace (serve_policy.h: first fit, oldest first,
+// younger ones may pass a head that does not fit a bounded number of times),
+// enqueues the request's whole stage sequence on the slot's stream, and
+// retires it when the slot's event completes, returning its workspace to the
+// pool.  Requests of different shapes therefore run concurrently on the
+// device, and a request that arrives while others are running starts as soon
+// as memory and a slot free up.  Sketches and intermediate factors live in
+// the pool, outputs in the caller's device buffers.  rlu_poll retires
+// finished tickets.
+//
+// One slot (max_inflight = 1): requests run one at a time with the device
+// to themselves, so their LU panels, whose blocks wait for each other, are
+// ordinary launches (every block resident) instead of cooperative ones,
+// which leave the device idle for about 11 us around each panel; and each
+// request's stage sequence is captured into a HIP graph on the slot stream
+// and launched as one graph.  The slot keeps the instantiated graphs of
+// recent launch topologies and updates one in place (hipGraphExecUpdate) for
+// a request with the same topology.  The stages run in order on the slot
+// stream, so a graph is one chain of nodes.  With more slots, requests share
+// the device, their panels are cooperative launches, as for rlu_factor, and
+// their stages are enqueued directly.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -29,6 +42,24 @@ namespace rlu {
 
 constexpr int kMaxInflight = 64;
 constexpr int kMaxBypass = 8;
+constexpr int kGraphCache = 8;  // instantiated graphs kept per slot
+
+// Launch topology of a request: requests with equal keys capture graphs of
+// the same shape, so an instantiated graph is first tried for them.
+struct GraphKey {
+  int64_t m, n, nnz;
+  int32_t layout, dtype, k, l, s, precision, k2, l2;
+  uint32_t flags;
+  bool operator==(const GraphKey &o) const {
+    return m == o.m && n == o.n && nnz == o.nnz && layout == o.layout && dtype == o.dtype && k == o.k &&
+           l == o.l && s == o.s && precision == o.precision && k2 == o.k2 && l2 == o.l2 && flags == o.flags;
+  }
+};
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec = nullptr;
+  uint64_t last_use = 0;
+};
 
 struct ServeRequest {
   uint64_t ticket;
@@ -42,7 +73,9 @@ struct ServeRequest {
 
 struct ServeSlot {
   hipStream_t st = nullptr;
+  AuxStream ax;            // auxiliary stream (same compute units) and its fork / join events
   hipEvent_t done = nullptr;
+  std::vector<GraphEntry> graphs;
   bool busy = false;
   uint64_t ticket = 0;
   size_t off = 0, bytes = 0;
@@ -59,6 +92,10 @@ struct TicketRec {
 
 struct ServeState {
   rlu_ctx_impl *cx = nullptr;
+  bool exclusive_slot = false;  // one slot with the device to itself: exclusive panels, graphs
+  DevCaps caps{};          // what the requests are planned for
+  uint64_t launches = 0;
+  uint64_t graph_hits = 0, graph_builds = 0, graph_fallbacks = 0;
   char *pool = nullptr;
   serve::PoolAlloc alloc;
   std::vector<ServeSlot> slots;
@@ -71,6 +108,89 @@ struct ServeState {
   bool stopping = false;
   int running = 0;
 };
+
+static GraphKey key_of(const ServeRequest &r) {
+  GraphKey k;
+  k.m = r.A.m; k.n = r.A.n; k.nnz = r.A.layout == RLU_CSR ? r.A.nnz : 0;
+  k.layout = r.A.layout; k.dtype = r.A.dtype;
+  k.k = r.p.k; k.l = r.p.l; k.s = r.p.s; k.precision = r.p.precision; k.k2 = r.p.k2; k.l2 = r.p.l2;
+  k.flags = r.p.flags;
+  return k;
+}
+
+// One request's stage sequence on its slot.  On the single exclusive slot:
+// captured into a graph and launched as one (an instantiated graph of the
+// slot updated in place when the topology allows, else a new one, the least
+// recently used dropped); if capture fails the stages are enqueued directly.
+static rlu_status launch_request(ServeState *s, ServeSlot &sl, const ServeRequest &r, void *ws) {
+  ExecEnv env;
+  env.caps = s->caps;
+  env.ax = sl.ax;
+  env.exclusive = s->exclusive_slot;
+  env.overlap = !s->exclusive_slot;
+  if (!s->exclusive_slot) return factor_enqueue(*s->cx, &r.A, &r.p, &r.out, ws, r.fp, sl.st, &env);
+  ++s->launches;
+  hipError_t e = hipStreamBeginCapture(sl.st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    ++s->graph_fallbacks;
+    return factor_enqueue(*s->cx, &r.A, &r.p, &r.out, ws, r.fp, sl.st, &env);
+  }
+  const rlu_status st = factor_enqueue(*s->cx, &r.A, &r.p, &r.out, ws, r.fp, sl.st, &env);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(sl.st, &g);
+  if (st != RLU_OK || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    if (st != RLU_OK) return st;
+    ++s->graph_fallbacks;
+    return factor_enqueue(*s->cx, &r.A, &r.p, &r.out, ws, r.fp, sl.st, &env);
+  }
+  const GraphKey key = key_of(r);
+  GraphEntry *hit = nullptr;
+  for (GraphEntry &ge : sl.graphs)
+    if (ge.key == key) { hit = &ge; break; }
+  hipGraphExec_t exec = nullptr;
+  if (hit) {
+    hipGraphNode_t err_node = nullptr;
+    hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+    if (hipGraphExecUpdate(hit->exec, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+      exec = hit->exec;
+      ++s->graph_hits;
+    } else {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(hit->exec);
+      hit->exec = nullptr;
+    }
+  }
+  if (!exec) {
+    e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipGraphDestroy(g);
+      if (hit) sl.graphs.erase(sl.graphs.begin() + (hit - sl.graphs.data()));
+      ++s->graph_fallbacks;
+      return factor_enqueue(*s->cx, &r.A, &r.p, &r.out, ws, r.fp, sl.st, &env);
+    }
+    ++s->graph_builds;
+    if (!hit) {
+      if ((int)sl.graphs.size() >= kGraphCache) {
+        size_t lru = 0;
+        for (size_t i = 1; i < sl.graphs.size(); ++i)
+          if (sl.graphs[i].last_use < sl.graphs[lru].last_use) lru = i;
+        (void)hipGraphExecDestroy(sl.graphs[lru].exec);
+        sl.graphs.erase(sl.graphs.begin() + lru);
+      }
+      sl.graphs.push_back(GraphEntry{key, nullptr, 0});
+      hit = &sl.graphs.back();
+    }
+    hit->exec = exec;
+  }
+  hit->last_use = s->launches;
+  (void)hipGraphDestroy(g);
+  e = hipGraphLaunch(exec, sl.st);
+  return e == hipSuccess ? RLU_OK : hip_fail(e, "hipGraphLaunch");
+}
 
 static void worker_main(ServeState *s) {
   (void)hipSetDevice(s->cx->caps.device);
@@ -104,7 +224,7 @@ static void worker_main(ServeState *s) {
       ++s->running;
       s->tickets[r.ticket].state = kRunning;
       lk.unlock();  // launching does not hold up rlu_submit / rlu_poll
-      rlu_status st = factor_enqueue(*s->cx, &r.A, &r.p, &r.out, s->pool + off, r.fp, sl.st);
+      rlu_status st = launch_request(s, sl, r, s->pool + off);
       std::string msg = st != RLU_OK ? rlu_last_error() : "";
       const hipError_t e = hipEventRecord(sl.done, sl.st);
       if (st == RLU_OK && e != hipSuccess) {
@@ -150,10 +270,15 @@ static rlu_status stop_state(rlu_ctx_impl &cx) {
   s->cv.notify_all();
   if (s->worker.joinable()) s->worker.join();
   for (ServeSlot &sl : s->slots) {
-    if (sl.st) {
-      (void)hipStreamSynchronize(sl.st);
-      (void)hipStreamDestroy(sl.st);
-    }
+    if (sl.st) (void)hipStreamSynchronize(sl.st);
+    if (sl.ax.aux && sl.ax.aux != sl.st) (void)hipStreamSynchronize(sl.ax.aux);
+    for (GraphEntry &ge : sl.graphs)
+      if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
+    sl.graphs.clear();
+    if (sl.ax.aux && sl.ax.aux != sl.st) (void)hipStreamDestroy(sl.ax.aux);
+    if (sl.st) (void)hipStreamDestroy(sl.st);
+    if (sl.ax.fork) (void)hipEventDestroy(sl.ax.fork);
+    if (sl.ax.join) (void)hipEventDestroy(sl.ax.join);
     if (sl.done) (void)hipEventDestroy(sl.done);
   }
   if (s->pool) (void)hipFree(s->pool);
@@ -190,9 +315,19 @@ rlu_status rlu_serve_start(rlu_ctx *ctx, size_t hbm_budget_bytes, int max_inflig
   }
   s->alloc.reset(bytes);
   s->slots.resize(max_inflight);
+  s->caps = cx.caps;
+  s->exclusive_slot = max_inflight == 1;  // the one slot has the device to itself
   for (ServeSlot &sl : s->slots) {
-    if ((e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess) {
+    e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+      if (s->exclusive_slot) sl.ax.aux = sl.st;  // its stages run in order on the slot stream
+      else e = hipStreamCreateWithFlags(&sl.ax.aux, hipStreamNonBlocking);
+    }
+    sl.ax.main = sl.st;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ax.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ax.join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    if (e != hipSuccess) {
       cx.serve = s;
       stop_state(cx);
       return hip_fail(e, "serving slot");
@@ -223,7 +358,7 @@ rlu_status rlu_submit(rlu_ctx *ctx, const rlu_matrix *A, const rlu_params *p, co
   if (p->flags & RLU_FLAG_EXCLUSIVE)  // requests in flight share the device by design
     return fail(RLU_ERR_INVALID_ARG, "RLU_FLAG_EXCLUSIVE is not available for served requests");
   ServeRequest r;
-  if ((st = plan_factor(cx, A, p, &r.fp)) != RLU_OK) return st;
+  if ((st = plan_factor(s->caps, A, p, &r.fp)) != RLU_OK) return st;
   r.A = *A;
   r.p = *p;
   r.out = *out;
@@ -255,6 +390,21 @@ rlu_status rlu_poll(rlu_ctx *ctx, uint64_t ticket) {
   const std::string msg = it->second.msg;
   s->tickets.erase(it);
   return st == RLU_OK ? RLU_OK : fail(st, "%s", msg.c_str());
+}
+
+rlu_status rlu_serve_stats(rlu_ctx *ctx, uint64_t *stats) {
+  if (!ctx || !stats) return fail(RLU_ERR_INVALID_ARG, "NULL argument");
+  ServeState *s = reinterpret_cast<rlu_ctx_impl *>(ctx)->serve;
+  if (!s) return fail(RLU_ERR_INVALID_ARG, "serving not started (rlu_serve_start)");
+  std::lock_guard<std::mutex> g(s->mu);
+  stats[0] = s->exclusive_slot ? 1u : 0u;
+  stats[1] = (uint64_t)s->caps.num_cu;
+  stats[2] = s->launches;
+  stats[3] = s->graph_hits;
+  stats[4] = s->graph_builds;
+  stats[5] = s->graph_fallbacks;
+  stats[6] = stats[7] = 0;
+  return RLU_OK;
 }
 
 rlu_status rlu_serve_stop(rlu_ctx *ctx) {

@@ -19,7 +19,8 @@
 // Contraction.  A^T is built once per call as CSC (column counts, scan,
 // scatter with atomic cursors); one wavefront per column then gathers rows of
 // Lhat.  The order of a column's entries follows the scatter, so W is
-// reproducible to rounding, not bit for bit.
+// reproducible to rounding, not bit for bit, unless the columns are sorted by
+// row after the scatter (RLU_FLAG_DETERMINISTIC).
 //
 // Column indices outside [0, n) and inconsistent row pointers are not
 // trusted: such entries are skipped and counted in rlu_info.bad_index.
@@ -32,20 +33,25 @@ __device__ inline int64_t clamp_ptr(int32_t p, int64_t nnz) {
   return p < 0 ? 0 : (p > nnz ? nnz : (int64_t)p);
 }
 
-template <int QPL, bool HAD>
+// GT: the cos table is read from global memory (s > kLdsMaxS) instead of LDS.
+template <int QPL, bool HAD, bool GT>
 __global__ __launch_bounds__(256) void k_sketch_csr(int64_t m, int64_t n, int64_t nnz,
                                                     const int32_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ col,
                                                     const double *__restrict__ val, int s, int l,
                                                     const uint32_t *__restrict__ code,
                                                     const int32_t *__restrict__ sel,
-                                                    const double2 *__restrict__ twp, double *__restrict__ Y,
+                                                    const double2 *__restrict__ twp,
+                                                    const double *__restrict__ gctab, double *__restrict__ Y,
                                                     int64_t ldy, int32_t *bad_index) {
-  extern __shared__ double ctab[];  // cos(2 pi k / s), k < s
+  extern __shared__ double lctab[];  // cos(2 pi k / s), k < s
   const int tid = threadIdx.x, lane = tid & 63;
   const int N = s >> 1;
-  for (int k = tid; k < s; k += 256) ctab[k] = (k < N) ? twp[k].x : -twp[k - N].x;
-  __syncthreads();
+  if (!GT && !HAD) {
+    for (int k = tid; k < s; k += 256) lctab[k] = (k < N) ? twp[k].x : -twp[k - N].x;
+    __syncthreads();
+  }
+  const double *ctab = GT ? gctab : lctab;
   const double rs = 1.0 / sqrt((double)s);
   const double r2s = sqrt(2.0) * rs;
   const uint32_t mask = (uint32_t)s - 1u;
@@ -106,26 +112,36 @@ __global__ __launch_bounds__(256) void k_sketch_csr(int64_t m, int64_t n, int64_
   if (bad) atomicAdd(bad_index, bad);
 }
 
+// outputs per lane of the CSR kernels: l <= 64 QPL, QPL in {1..9, 12, 16}
+static int csr_qpl(int l) {
+  const int q = (int)ceil_div(l, 64);
+  return q <= 9 ? q : (q <= 12 ? 12 : (q <= 16 ? 16 : 0));
+}
+
 hipError_t launch_sketch_csr(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t *col,
                              const double *val, int64_t nnz, int s, int l, const uint32_t *code,
-                             const int32_t *sel, const double2 *twf, const double2 *twp, double *Y,
+                             const int32_t *sel, const double2 *twp, const double *gctab, double *Y,
                              int64_t ldy, int32_t *bad_index, int num_cu, bool hadamard, hipStream_t st) {
-  (void)twf;
-  const int qpl = (int)ceil_div(l, 64);
+  const int qpl = csr_qpl(l);
+  const bool gt = !hadamard && s > kLdsMaxS;
+  if (gt && !gctab) return hipErrorInvalidValue;
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(m, 4), (int64_t)num_cu * 8));
-  const size_t lds = (size_t)s * sizeof(double);
-#define RLU_CSR_Q(Q)                                                                                    \
-  case Q:                                                                                               \
-    if (hadamard)                                                                                       \
-      hipLaunchKernelGGL((k_sketch_csr<Q, true>), dim3(blocks), dim3(256), lds, st, m, n, nnz, row_ptr,  \
-                         col, val, s, l, code, sel, twp, Y, ldy, bad_index);                            \
-    else                                                                                                \
-      hipLaunchKernelGGL((k_sketch_csr<Q, false>), dim3(blocks), dim3(256), lds, st, m, n, nnz, row_ptr, \
-                         col, val, s, l, code, sel, twp, Y, ldy, bad_index);                            \
+  const size_t lds = hadamard || gt ? 0 : (size_t)s * sizeof(double);
+#define RLU_CSR_Q(Q)                                                                                       \
+  case Q:                                                                                                  \
+    if (hadamard)                                                                                          \
+      hipLaunchKernelGGL((k_sketch_csr<Q, true, false>), dim3(blocks), dim3(256), lds, st, m, n, nnz,      \
+                         row_ptr, col, val, s, l, code, sel, twp, gctab, Y, ldy, bad_index);               \
+    else if (gt)                                                                                           \
+      hipLaunchKernelGGL((k_sketch_csr<Q, false, true>), dim3(blocks), dim3(256), lds, st, m, n, nnz,      \
+                         row_ptr, col, val, s, l, code, sel, twp, gctab, Y, ldy, bad_index);               \
+    else                                                                                                   \
+      hipLaunchKernelGGL((k_sketch_csr<Q, false, false>), dim3(blocks), dim3(256), lds, st, m, n, nnz,     \
+                         row_ptr, col, val, s, l, code, sel, twp, gctab, Y, ldy, bad_index);               \
     break;
   switch (qpl) {
     RLU_CSR_Q(1) RLU_CSR_Q(2) RLU_CSR_Q(3) RLU_CSR_Q(4) RLU_CSR_Q(5) RLU_CSR_Q(6) RLU_CSR_Q(7)
-    RLU_CSR_Q(8) RLU_CSR_Q(9)
+    RLU_CSR_Q(8) RLU_CSR_Q(9) RLU_CSR_Q(12) RLU_CSR_Q(16)
     default: return hipErrorInvalidValue;
   }
 #undef RLU_CSR_Q
@@ -133,12 +149,11 @@ hipError_t launch_sketch_csr(int64_t m, int64_t n, const int32_t *row_ptr, const
 }
 
 void sketch_csr_set_attrs() {
-#define RLU_CSR_A(Q)                                                                                            \
-  (void)hipFuncSetAttribute((const void *)k_sketch_csr<Q, false>, hipFuncAttributeMaxDynamicSharedMemorySize,  \
-                            kMaxS * 8);                                                                          \
-  (void)hipFuncSetAttribute((const void *)k_sketch_csr<Q, true>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxS * 8);
+#define RLU_CSR_A(Q)                                                                                      \
+  (void)hipFuncSetAttribute((const void *)k_sketch_csr<Q, false, false>,                                 \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMaxS * 8);
   RLU_CSR_A(1) RLU_CSR_A(2) RLU_CSR_A(3) RLU_CSR_A(4) RLU_CSR_A(5) RLU_CSR_A(6) RLU_CSR_A(7) RLU_CSR_A(8)
-  RLU_CSR_A(9)
+  RLU_CSR_A(9) RLU_CSR_A(12) RLU_CSR_A(16)
 #undef RLU_CSR_A
 }
 
@@ -163,67 +178,224 @@ hipError_t launch_csr_check(const rlu_matrix *A, int validate_cols, rlu_info *in
 
 // ---- CSC (A^T) build and the sparse contraction -------------------------------------
 
-__global__ void k_col_count(int64_t m, int64_t n, int64_t nnz, const int32_t *__restrict__ row_ptr,
-                            const int32_t *__restrict__ col, int32_t *__restrict__ cnt) {
-  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-  const int lane = threadIdx.x & 63;
-  for (int64_t i = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); i < m; i += waves) {
-    const int64_t lo = clamp_ptr(row_ptr[i], nnz), hi = max(lo, clamp_ptr(row_ptr[i + 1], nnz));
-    for (int64_t k = lo + lane; k < hi; k += 64) {
-      const int32_t j = col[k];
-      if (j >= 0 && j < n) atomicAdd(&cnt[j], 1);
+// CSC copy of A by a two-level counting sort with no device-wide atomics
+// (a device-scope atomic on this chip is performed beyond the per-die L2
+// caches, so one per nonzero into n shared counters is slow).  The nonzeros
+// [0, nnz) are cut into kCscChunks equal chunks and the columns into ranges
+// of kCscRange; block (b, r) owns entry chunk b and column range r, whose
+// counters fit in LDS.  Every entry is enumerated exactly once whatever the
+// row pointers hold, so the positions can never pass nnz.
+//   1. k_csc_hist: LDS counts of the chunk's entries per column, stored as
+//      hist[b][c] (coalesced);
+//   2. k_csc_colscan: per column, the exclusive prefix over the chunks in
+//      place and the column's total; a scan of the totals gives colptr;
+//   3. k_csc_place: the block's LDS cursors start at colptr[c] + hist[b][c]
+//      and the block writes its entries there; each thread takes a contiguous
+//      run of the chunk, finds the row of its first entry by a binary search
+//      of the row pointers and follows the rows along from there.
+// A column's entries come chunk by chunk, so in increasing row order across
+// chunks; within one chunk they follow the LDS cursor increments (sorted
+// afterwards in deterministic mode).
+constexpr int kCscRange = 16384;
+constexpr int kCscChunks = 128;
+constexpr int kScanTile = 4096;
+
+__global__ __launch_bounds__(256) void k_csc_hist(int64_t n, int64_t nnz, const int32_t *__restrict__ col,
+                                                  int32_t *__restrict__ hist) {
+  __shared__ int32_t h[kCscRange];
+  const int tid = threadIdx.x;
+  const int B = gridDim.x, b = blockIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.y * kCscRange;
+  const int cw = (int)min<int64_t>(kCscRange, n - c0);
+  for (int i = tid; i < cw; i += 256) h[i] = 0;
+  __syncthreads();
+  const int64_t k0 = nnz * b / B, k1 = nnz * (b + 1) / B;
+  for (int64_t k = k0 + tid; k < k1; k += 256) {
+    const int64_t c = (int64_t)col[k] - c0;
+    if (c >= 0 && c < cw) atomicAdd(&h[c], 1);
+  }
+  __syncthreads();
+  for (int i = tid; i < cw; i += 256) hist[(int64_t)b * n + c0 + i] = h[i];
+}
+
+// per column: exclusive prefix over the chunks in place, the total in tot
+__global__ void k_csc_colscan(int64_t n, int B, int32_t *__restrict__ hist, int32_t *__restrict__ tot) {
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
+    int32_t run = 0;
+    for (int b = 0; b < B; ++b) {
+      const int32_t x = hist[(int64_t)b * n + c];
+      hist[(int64_t)b * n + c] = run;
+      run += x;
     }
+    tot[c] = run;
   }
 }
 
-// exclusive scan of n counts (one block): colptr[0..n]
-__global__ __launch_bounds__(1024) void k_scan(int64_t n, const int32_t *__restrict__ cnt, int32_t *__restrict__ colptr) {
+// scan, phase 1: the sum of each tile of kScanTile counts
+__global__ __launch_bounds__(256) void k_scan_tiles(int64_t total, const int32_t *__restrict__ v,
+                                                    int32_t *__restrict__ tile_sum) {
+  __shared__ int32_t ws[4];
+  const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+  int32_t acc = 0;
+  for (int64_t i = t0 + threadIdx.x; i < min(total, t0 + kScanTile); i += 256) acc += v[i];
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// scan, phase 2 (one block): exclusive scan of the tile sums in place
+__global__ __launch_bounds__(1024) void k_scan_tile_sums(int ntiles, int32_t *__restrict__ tile_sum) {
   __shared__ int32_t part[1024];
   const int tid = threadIdx.x;
-  const int64_t per = ceil_div(n, 1024);
-  const int64_t a = tid * per, b = min(n, a + per);
-  int32_t s = 0;
-  for (int64_t i = a; i < b; ++i) s += cnt[i];
-  part[tid] = s;
+  const int per = (ntiles + 1023) / 1024;
+  const int a = min(ntiles, tid * per), e = min(ntiles, a + per);
+  int32_t run = 0;
+  for (int i = a; i < e; ++i) run += tile_sum[i];
+  part[tid] = run;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
-    const int32_t v = tid >= off ? part[tid - off] : 0;
+    const int32_t x = tid >= off ? part[tid - off] : 0;
     __syncthreads();
-    part[tid] += v;
+    part[tid] += x;
     __syncthreads();
   }
-  int32_t run = tid ? part[tid - 1] : 0;
-  for (int64_t i = a; i < b; ++i) {
-    colptr[i] = run;
-    run += cnt[i];
+  int32_t base = tid ? part[tid - 1] : 0;
+  for (int i = a; i < e; ++i) {
+    const int32_t x = tile_sum[i];
+    tile_sum[i] = base;
+    base += x;
   }
-  if (tid == 1023) colptr[n] = part[1023];
 }
 
-__global__ void k_col_scatter(int64_t m, int64_t n, int64_t nnz, const int32_t *__restrict__ row_ptr,
-                              const int32_t *__restrict__ col, const double *__restrict__ val,
-                              const int32_t *__restrict__ colptr, int32_t *__restrict__ cursor,
-                              int32_t *__restrict__ crow, double *__restrict__ cval) {
-  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-  const int lane = threadIdx.x & 63;
-  for (int64_t i = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); i < m; i += waves) {
-    const int64_t lo = clamp_ptr(row_ptr[i], nnz), hi = max(lo, clamp_ptr(row_ptr[i + 1], nnz));
-    for (int64_t k = lo + lane; k < hi; k += 64) {
-      const int32_t j = col[k];
-      if (j >= 0 && j < n) {
-        const int32_t p = colptr[j] + atomicAdd(&cursor[j], 1);
-        crow[p] = (int32_t)i;
-        cval[p] = val[k];
+// scan, phase 3: out[i] = exclusive prefix of v (each tile from its base);
+// out[total] = the sum
+__global__ __launch_bounds__(256) void k_scan_apply(int64_t total, const int32_t *__restrict__ v,
+                                                    const int32_t *__restrict__ tile_sum, int32_t *__restrict__ out) {
+  __shared__ int32_t wsum[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+  int32_t base = tile_sum[blockIdx.x];
+  for (int64_t c0 = t0; c0 < min(total, t0 + kScanTile); c0 += 256) {
+    const int64_t i = c0 + tid;
+    const int32_t x = i < total ? v[i] : 0;
+    int32_t incl = x;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t y = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += y;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int32_t before = base;
+    for (int w = 0; w < wv; ++w) before += wsum[w];
+    if (i < total) out[i] = before + incl - x;
+    const int32_t round = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    base += round;
+  }
+  if (blockIdx.x == gridDim.x - 1 && tid == 0) out[total] = base;
+}
+
+// the row of entry k: the last row i with row_ptr[i] <= k (clamped to [0, m))
+__device__ inline int64_t row_of(int64_t m, const int32_t *__restrict__ row_ptr, int64_t k) {
+  int64_t lo = 0, hi = m - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if ((int64_t)row_ptr[mid] <= k) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_csc_place(int64_t m, int64_t n, int64_t nnz,
+                                                   const int32_t *__restrict__ row_ptr,
+                                                   const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                   const int32_t *__restrict__ colptr, const int32_t *__restrict__ hist,
+                                                   int32_t *__restrict__ crow, double *__restrict__ cval) {
+  __shared__ int32_t cur[kCscRange];
+  const int tid = threadIdx.x;
+  const int B = gridDim.x, b = blockIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.y * kCscRange;
+  const int cw = (int)min<int64_t>(kCscRange, n - c0);
+  for (int i = tid; i < cw; i += 256) cur[i] = colptr[c0 + i] + hist[(int64_t)b * n + c0 + i];
+  __syncthreads();
+  // each thread a contiguous run of the chunk's entries, so that its row is
+  // found once by binary search and then only moves forward
+  const int64_t k0 = nnz * b / B, k1 = nnz * (b + 1) / B, len = k1 - k0;
+  const int64_t ka = k0 + len * tid / 256, kb = k0 + len * (tid + 1) / 256;
+  int64_t row = ka < kb ? row_of(m, row_ptr, ka) : 0;
+  for (int64_t k = ka; k < kb; ++k) {
+    const int64_t c = (int64_t)col[k] - c0;
+    if (c < 0 || c >= cw) continue;
+    while (row + 1 < m && (int64_t)row_ptr[row + 1] <= k) ++row;
+    const int32_t p = atomicAdd(&cur[c], 1);
+    crow[p] = (int32_t)row;
+    cval[p] = val[k];
+  }
+}
+
+// Sorts every column's entries of the CSC copy by row (RLU_FLAG_DETERMINISTIC):
+// the scatter leaves them in arrival order, which changes run to run.  The
+// rows of a column are distinct, so the sorted order is unique.  One block per
+// column; a bitonic sort in its ascending-only form (at the first step of each
+// merge the partner is i ^ (k - 1), then i ^ j), so positions past the
+// column's end act as +infinity and never move.  Columns of up to kSortLds
+// entries are sorted in LDS, longer ones in place in global memory.
+constexpr int kSortLds = 2048;
+__global__ __launch_bounds__(256) void k_csc_sort(int64_t n, const int32_t *__restrict__ colptr,
+                                                  int32_t *__restrict__ crow, double *__restrict__ cval) {
+  __shared__ int32_t sr[kSortLds];
+  __shared__ double sv[kSortLds];
+  const int tid = threadIdx.x;
+  for (int64_t j = blockIdx.x; j < n; j += gridDim.x) {
+    const int32_t a = colptr[j], len = colptr[j + 1] - a;
+    if (len < 2) continue;  // uniform over the block
+    const bool in_lds = len <= kSortLds;
+    int32_t *r = in_lds ? sr : crow + a;
+    double *v = in_lds ? sv : cval + a;
+    if (in_lds) {
+      for (int i = tid; i < len; i += 256) {
+        sr[i] = crow[a + i];
+        sv[i] = cval[a + i];
       }
     }
+    __syncthreads();
+    int P = 1;
+    while (P < len) P <<= 1;
+    for (int k = 2; k <= P; k <<= 1) {
+      for (int jj = k >> 1; jj > 0; jj >>= 1) {
+        for (int i = tid; i < P; i += 256) {
+          const int q = jj == (k >> 1) ? (i ^ (k - 1)) : (i ^ jj);
+          if (q > i && q < len && r[i] > r[q]) {
+            const int32_t tr = r[i];
+            r[i] = r[q];
+            r[q] = tr;
+            const double tv = v[i];
+            v[i] = v[q];
+            v[q] = tv;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if (in_lds) {
+      for (int i = tid; i < len; i += 256) {
+        crow[a + i] = sr[i];
+        cval[a + i] = sv[i];
+      }
+    }
+    __syncthreads();
   }
 }
 
 // W^T[j][:] = sum over column j of A: v * Lhat[row][:]   (one wavefront per column)
+// The column's entries are taken UNR at a time: the UNR rows of Lhat are all
+// loaded before any is used (UNR x QPL loads in flight per lane), then added
+// in entry order, so the sums are the same as one entry at a time.
 template <int QPL>
 __global__ __launch_bounds__(256) void k_spmm_t(int64_t n, int l, const int32_t *__restrict__ colptr,
                                                 const int32_t *__restrict__ crow, const double *__restrict__ cval,
                                                 const double *__restrict__ Lhat, double *__restrict__ Wt) {
+  constexpr int UNR = QPL <= 2 ? 8 : (QPL <= 4 ? 4 : 2);
   const int lane = threadIdx.x & 63;
   const int64_t waves = (int64_t)gridDim.x * 4;
   for (int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); j < n; j += waves) {
@@ -235,18 +407,30 @@ __global__ __launch_bounds__(256) void k_spmm_t(int64_t n, int l, const int32_t 
       const int32_t p = base + lane;
       const int32_t r = p < b ? crow[p] : 0;
       const double v = p < b ? cval[p] : 0.0;
+      const int64_t bits = __double_as_longlong(v);
       const int cnt = min(64, b - base);
-      for (int e = 0; e < cnt; ++e) {
-        const int re = __builtin_amdgcn_readlane(r, e);
-        const int64_t bits = __double_as_longlong(v);
-        const int lo32 = __builtin_amdgcn_readlane((int)(uint32_t)bits, e);
-        const int hi32 = __builtin_amdgcn_readlane((int)(uint32_t)(bits >> 32), e);
-        const double ve = __longlong_as_double(((int64_t)(uint32_t)hi32 << 32) | (uint32_t)lo32);
-        const double *lr = Lhat + (int64_t)re * l;
+      for (int e0 = 0; e0 < cnt; e0 += UNR) {
+        double lv[UNR][QPL], ve[UNR];
 #pragma unroll
-        for (int t = 0; t < QPL; ++t) {
-          const int q = lane + 64 * t;
-          if (q < l) acc[t] += ve * lr[q];
+        for (int u = 0; u < UNR; ++u) {
+          const int eu = min(e0 + u, cnt - 1);  // uniform; past the end: a repeat, weighted 0
+          const int re = __builtin_amdgcn_readlane(r, eu);
+          const int lo32 = __builtin_amdgcn_readlane((int)(uint32_t)bits, eu);
+          const int hi32 = __builtin_amdgcn_readlane((int)(uint32_t)(bits >> 32), eu);
+          ve[u] = e0 + u < cnt ? __longlong_as_double(((int64_t)(uint32_t)hi32 << 32) | (uint32_t)lo32) : 0.0;
+          const double *lr = Lhat + (int64_t)re * l;
+#pragma unroll
+          for (int t = 0; t < QPL; ++t) {
+            const int q = lane + 64 * t;
+            lv[u][t] = q < l ? lr[q] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          if (e0 + u < cnt) {
+#pragma unroll
+            for (int t = 0; t < QPL; ++t) acc[t] += ve[u] * lv[u][t];
+          }
         }
       }
     }
@@ -258,27 +442,43 @@ __global__ __launch_bounds__(256) void k_spmm_t(int64_t n, int l, const int32_t 
   }
 }
 
+static int64_t csc_tiles(int64_t n) { return ceil_div(n, kScanTile); }
+
 size_t csc_scratch_bytes(int64_t n, int64_t nnz) {
-  return align_up((size_t)(n + 1) * 4, 256) * 3 + align_up((size_t)nnz * 4, 256) + align_up((size_t)nnz * 8, 256);
+  return align_up((size_t)n * kCscChunks * 4, 256) + align_up((size_t)n * 4, 256) +
+         align_up((size_t)csc_tiles(n) * 4, 256) + align_up((size_t)(n + 1) * 4, 256) +
+         align_up((size_t)nnz * 4, 256) + align_up((size_t)nnz * 8, 256);
 }
 
 hipError_t build_csc(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
-                     int64_t nnz, void *scratch, int num_cu, hipStream_t st, CscView *out) {
+                     int64_t nnz, void *scratch, int num_cu, bool sorted, hipStream_t st, CscView *out) {
   char *w = reinterpret_cast<char *>(scratch);
-  const size_t nb4 = align_up((size_t)(n + 1) * 4, 256);
-  int32_t *cnt = reinterpret_cast<int32_t *>(w);
-  int32_t *colptr = reinterpret_cast<int32_t *>(w + nb4);
-  int32_t *cursor = reinterpret_cast<int32_t *>(w + 2 * nb4);
-  int32_t *crow = reinterpret_cast<int32_t *>(w + 3 * nb4);
-  double *cval = reinterpret_cast<double *>(w + 3 * nb4 + align_up((size_t)nnz * 4, 256));
-  hipError_t e;
-  if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(cnt), 0u, n + 1, st)) != hipSuccess) return e;
-  if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(cursor), 0u, n + 1, st)) != hipSuccess) return e;
-  const int rblocks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(m, 4), (int64_t)num_cu * 16));
-  hipLaunchKernelGGL(k_col_count, dim3(rblocks), dim3(256), 0, st, m, n, nnz, row_ptr, col, cnt);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, n, cnt, colptr);
-  hipLaunchKernelGGL(k_col_scatter, dim3(rblocks), dim3(256), 0, st, m, n, nnz, row_ptr, col, val, colptr,
-                     cursor, crow, cval);
+  const int64_t ntiles = csc_tiles(n);
+  if (ntiles > 1024 * 1024) return hipErrorInvalidValue;
+  int32_t *hist = reinterpret_cast<int32_t *>(w);
+  w += align_up((size_t)n * kCscChunks * 4, 256);
+  int32_t *tot = reinterpret_cast<int32_t *>(w);
+  w += align_up((size_t)n * 4, 256);
+  int32_t *tsum = reinterpret_cast<int32_t *>(w);
+  w += align_up((size_t)ntiles * 4, 256);
+  int32_t *colptr = reinterpret_cast<int32_t *>(w);
+  w += align_up((size_t)(n + 1) * 4, 256);
+  int32_t *crow = reinterpret_cast<int32_t *>(w);
+  w += align_up((size_t)nnz * 4, 256);
+  double *cval = reinterpret_cast<double *>(w);
+  const dim3 grid(kCscChunks, (unsigned)ceil_div(n, kCscRange));
+  hipLaunchKernelGGL(k_csc_hist, grid, dim3(256), 0, st, n, nnz, col, hist);
+  const int cblocks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(n, 256)));
+  hipLaunchKernelGGL(k_csc_colscan, dim3(cblocks), dim3(256), 0, st, n, kCscChunks, hist, tot);
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(256), 0, st, n, tot, tsum);
+  hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(1024), 0, st, (int)ntiles, tsum);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(256), 0, st, n, tot, tsum, colptr);
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_csc_place, grid, dim3(256), 0, st, m, n, nnz, row_ptr, col, val, colptr, hist, crow, cval);
+  if (sorted) {
+    const int sblocks = (int)std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)num_cu * 8));
+    hipLaunchKernelGGL(k_csc_sort, dim3(sblocks), dim3(256), 0, st, n, colptr, crow, cval);
+  }
   out->colptr = colptr;
   out->crow = crow;
   out->cval = cval;
@@ -287,13 +487,13 @@ hipError_t build_csc(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t
 
 hipError_t contraction_csr(int64_t m, int64_t n, int l, const int32_t *row_ptr, const int32_t *col,
                            const double *val, int64_t nnz, const double *Lhat, double *Wt, void *scratch,
-                           int num_cu, hipStream_t st) {
+                           int num_cu, bool sorted, hipStream_t st) {
   CscView cs;
-  hipError_t e = build_csc(m, n, row_ptr, col, val, nnz, scratch, num_cu, st, &cs);
+  hipError_t e = build_csc(m, n, row_ptr, col, val, nnz, scratch, num_cu, sorted, st, &cs);
   if (e != hipSuccess) return e;
   const int32_t *colptr = cs.colptr, *crow = cs.crow;
   const double *cval = cs.cval;
-  const int qpl = (int)ceil_div(l, 64);
+  const int qpl = csr_qpl(l);
   const int cblocks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 4), (int64_t)num_cu * 16));
 #define RLU_SPMM_Q(Q)                                                                                  \
   case Q:                                                                                              \
@@ -301,7 +501,7 @@ hipError_t contraction_csr(int64_t m, int64_t n, int l, const int32_t *row_ptr, 
     break;
   switch (qpl) {
     RLU_SPMM_Q(1) RLU_SPMM_Q(2) RLU_SPMM_Q(3) RLU_SPMM_Q(4) RLU_SPMM_Q(5) RLU_SPMM_Q(6) RLU_SPMM_Q(7)
-    RLU_SPMM_Q(8) RLU_SPMM_Q(9)
+    RLU_SPMM_Q(8) RLU_SPMM_Q(9) RLU_SPMM_Q(12) RLU_SPMM_Q(16)
     default: return hipErrorInvalidValue;
   }
 #undef RLU_SPMM_Q

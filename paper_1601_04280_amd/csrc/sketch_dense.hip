@@ -170,8 +170,172 @@ __global__ __launch_bounds__(kSketchThreads) void k_sketch_dense(
 }
 
 // ---------------------------------------------------------------------------
-// Wave-specialised form (s <= 2048, aligned rows whose length is a multiple of
-// the vector width): blocks of four waves, four blocks per CU.  Three waves
+// Bucket-ordered form (RLU_FLAG_DETERMINISTIC).  The atomic forms above add a
+// row's values into its buckets in whatever order the waves reach LDS, so the
+// bucket sums are reproducible only to rounding.  Here every bucket sum is
+// formed in ascending column order, as the definition of Section 2.2 lists
+// the columns: y0[b] = ((c_j1 A[i, j1] + c_j2 A[i, j2]) + ...), j1 < j2 < ...,
+// c_j the folded sign, so the result is the same on every run.
+//
+// Tables (k_ordered_tables, once per call): the columns are cut into chunks
+// of C (a power of two, C <= min(s, 8192)); inside chunk c they are listed by
+// bucket, ascending column within a bucket:
+//   blist[c C + p] = column - c C, bit 31 set for a negative folded sign;
+//   boff[c (s + 1) + b] = start of bucket b's run in blist (absolute index),
+//   boff[c (s + 1) + s] = end of the chunk's entries.
+// One block per chunk sorts the keys (bucket, column) in LDS (bitonic; the
+// keys are distinct, so the order is unique) and finds each bucket's start by
+// binary search.
+// Kernel: one block per row at a time.  Thread t owns buckets b = t mod TH.
+// Per chunk the row's C values are staged in LDS (in the second half of the
+// transform's buffer, idle until the transform) and each thread adds its
+// buckets' entries in list order; then the transform as in k_sketch_dense.
+// ---------------------------------------------------------------------------
+constexpr int kOrdThreads = 256;
+constexpr int kOrdMaxChunk = 8192;  // 13 bits of column within a chunk
+constexpr int kOrdColBits = 13;
+
+int ordered_chunk(int s) { return std::min(s, kOrdMaxChunk); }
+
+__global__ __launch_bounds__(kOrdThreads) void k_ordered_tables(int64_t n, int s, int C,
+                                                                const uint32_t *__restrict__ code,
+                                                                uint32_t *__restrict__ blist,
+                                                                int32_t *__restrict__ boff) {
+  extern __shared__ uint32_t key[];  // C keys: bucket << 13 | column within the chunk
+  const int tid = threadIdx.x;
+  const int64_t c = blockIdx.x, j0 = c * (int64_t)C;
+  const int len = (int)min<int64_t>(C, n - j0);
+  for (int e = tid; e < C; e += kOrdThreads)
+    key[e] = e < len ? (code_bucket(code[j0 + e]) << kOrdColBits) | (uint32_t)e : 0xFFFFFFFFu;
+  __syncthreads();
+  for (int k = 2; k <= C; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < C; i += kOrdThreads) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint32_t a = key[i], b = key[ixj];
+          if ((a > b) == ((i & k) == 0)) {
+            key[i] = b;
+            key[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int p = tid; p < len; p += kOrdThreads) {
+    const uint32_t e = key[p] & ((1u << kOrdColBits) - 1u);
+    blist[j0 + p] = e | (code[j0 + e] & 0x80000000u);
+  }
+  int32_t *off = boff + c * (int64_t)(s + 1);
+  for (int b = tid; b <= s; b += kOrdThreads) {
+    int lo = 0, hi = len;  // first p with bucket(key[p]) >= b
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((key[mid] >> kOrdColBits) < (uint32_t)b) lo = mid + 1; else hi = mid;
+    }
+    off[b] = (int32_t)(j0 + lo);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kOrdThreads) void k_sketch_ordered(
+    int64_t m, int64_t n, const T *__restrict__ A, int64_t lda, int s, int log2N, int l, int C,
+    const uint32_t *__restrict__ blist, const int32_t *__restrict__ boff, const int32_t *__restrict__ sel,
+    const double2 *__restrict__ twf, const double2 *__restrict__ twp, double *__restrict__ Y, int64_t ldy,
+    int hadamard) {
+  extern __shared__ double2 lds2[];
+  constexpr int TH = kOrdThreads;
+  const int N = s >> 1;
+  const int tid = threadIdx.x;
+  const double rs = 1.0 / sqrt((double)s);
+  const double r2s = sqrt(2.0) * rs;
+  double2 *buf = lds2;
+  double2 *tab = lds2 + 2 * N;
+  const int b = log2N >> 1, nlo = 1 << b, nhi = N >> b;
+  int32_t *sel_s = reinterpret_cast<int32_t *>(tab + 2 * (nlo + nhi));
+  for (int i = tid; i < nlo; i += TH) {
+    tab[i] = twf[i];
+    tab[nlo + nhi + i] = twp[i];
+  }
+  for (int i = tid; i < nhi; i += TH) {
+    tab[nlo + i] = twf[i << b];
+    tab[2 * nlo + nhi + i] = twp[i << b];
+  }
+  for (int q = tid; q < l; q += TH) sel_s[q] = sel[q];
+  const TwSplit tf{tab, tab + nlo, b, nlo - 1};
+  const TwSplit tp{tab + nlo + nhi, tab + 2 * nlo + nhi, b, nlo - 1};
+  double *y0 = reinterpret_cast<double *>(buf);
+  double *chunk = reinterpret_cast<double *>(buf + N);  // C <= s values
+  const int64_t nch = (n + C - 1) / C;
+  for (int64_t row = blockIdx.x; row < m; row += gridDim.x) {
+    const T *a = A + row * lda;
+    for (int64_t c = 0; c < nch; ++c) {
+      const int64_t j0 = c * C;
+      const int len = (int)min<int64_t>(C, n - j0);
+      for (int e = tid; e < len; e += TH) chunk[e] = to_f64(__builtin_nontemporal_load(a + j0 + e));
+      __syncthreads();
+      const int32_t *off = boff + c * (int64_t)(s + 1);
+      for (int bk = tid; bk < s; bk += TH) {
+        const int p0 = off[bk], p1 = off[bk + 1];
+        double acc = c == 0 ? 0.0 : y0[bk];
+        for (int p = p0; p < p1; ++p) {
+          const uint32_t e = blist[p];
+          const double v = chunk[e & 0x7FFFFFFFu];
+          acc += (e >> 31) ? -v : v;
+        }
+        y0[bk] = acc;
+      }
+      __syncthreads();  // the chunk is read before the next one lands
+    }
+    double *yrow = Y + row * ldy;
+    if (hadamard) {
+      fwht_block<TH>(y0, log2N + 1, tid);
+      for (int q = tid; q < l; q += TH) yrow[q] = y0[sel_s[q]] * rs;
+    } else {
+      const double2 *Z = fft_lds<TH>(buf, buf + N, N, log2N, tf);
+      for (int q = tid; q < l; q += TH) yrow[q] = real_coord(Z, s, sel_s[q], tp, rs, r2s);
+    }
+    __syncthreads();
+  }
+}
+
+size_t ordered_tables_bytes(int64_t n, int s) {
+  const int C = ordered_chunk(s);
+  const int64_t nch = (n + C - 1) / C;
+  return align_up((size_t)n * 4, 256) + (size_t)nch * (size_t)(s + 1) * 4;
+}
+
+hipError_t launch_sketch_ordered(int64_t m, int64_t n, const void *A, int dtype, int64_t lda, int s, int l,
+                                 const uint32_t *code, const int32_t *sel, const double2 *twf, const double2 *twp,
+                                 void *tables, double *Y, int64_t ldy, int num_cu, bool hadamard, hipStream_t st) {
+  const int C = ordered_chunk(s);
+  const int64_t nch = (n + C - 1) / C;
+  if (nch > INT32_MAX || n > INT32_MAX) return hipErrorInvalidValue;
+  uint32_t *blist = reinterpret_cast<uint32_t *>(tables);
+  int32_t *boff = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(tables) + align_up((size_t)n * 4, 256));
+  hipLaunchKernelGGL(k_ordered_tables, dim3((unsigned)nch), dim3(kOrdThreads), (size_t)C * 4, st, n, s, C, code,
+                     blist, boff);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = sketch_lds_bytes(s, l);
+  const int per_cu = std::max<int>(1, (int)std::min<size_t>(8, (160 * 1024) / lds));
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)num_cu * per_cu));
+  const int log2N = ilog2_exact(s / 2);
+  const int had = hadamard ? 1 : 0;
+  if (dtype == RLU_F64)
+    hipLaunchKernelGGL(k_sketch_ordered<double>, dim3(grid), dim3(kOrdThreads), lds, st, m, n, (const double *)A,
+                       lda, s, log2N, l, C, blist, boff, sel, twf, twp, Y, ldy, had);
+  else
+    hipLaunchKernelGGL(k_sketch_ordered<float>, dim3(grid), dim3(kOrdThreads), lds, st, m, n, (const float *)A, lda,
+                       s, log2N, l, C, blist, boff, sel, twf, twp, Y, ldy, had);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Wave-specialised form (s <= 4096, aligned rows whose length is a multiple of
+// the vector width): blocks of four waves, four blocks per CU (two at
+// s = 4096, whose two row buffers take 70 KB of LDS).  Three waves
 // stream row r with 16-byte loads, a chunk of the row in flight per thread,
 // and scatter it into LDS buffer r & 1; the fourth meanwhile transforms row
 // r - 1 in the other buffer,
@@ -182,11 +346,11 @@ __global__ __launch_bounds__(kSketchThreads) void k_sketch_dense(
 // passes' strided accesses spread over the LDS banks.
 constexpr int kWsSem = 192;                 // streaming threads (three waves)
 constexpr int kWsThreads = kWsSem + 64;     // plus the transform wave: one wave per SIMD
-constexpr int kWsMaxN = 1024;               // complex length (s <= 2048)
+constexpr int kWsMaxN = 2048;               // complex length (s <= 4096; two blocks per CU at s = 4096)
 
 __host__ __device__ inline int padc(int i) { return i + (i >> 4); }
 
-// In-place decimation-in-frequency transform of N <= 1024 complex values by
+// In-place decimation-in-frequency transform of N <= 2048 complex values by
 // one wave (kernel e^{-2 pi i / N}).  Passes of radix 16 while the block size
 // M is at least 16, then radix 4, or radix 2 then 4, or 2, for what is left
 // (1024 = 16 16 4).  A pass of radix R over blocks of size M = R S computes,
@@ -194,8 +358,9 @@ __host__ __device__ inline int padc(int i) { return i + (i >> 4); }
 //   y_m = (sum_r a_r e^{-2 pi i r m / R}) w^{j m},  w = e^{-2 pi i / M},
 // and stores y_m back at z[g + j + m S].  A butterfly reads and writes the
 // same positions, so one buffer suffices, and the spectrum comes out in
-// digit-reversed order (dif_pos).  A radix-16 pass has N/16 <= 64 butterflies:
-// one per lane, its 16 values in registers, one LDS round trip per pass.
+// digit-reversed order (dif_pos).  A radix-16 pass has N/16 <= 128 butterflies:
+// one or two per lane, 16 values in registers each, one LDS round trip per
+// pass.
 __device__ inline void dft4(double2 &x0, double2 &x1, double2 &x2, double2 &x3) {
   const double2 s02 = cadd(x0, x2), d02 = csub(x0, x2), s13 = cadd(x1, x3), d13 = csub(x1, x3);
   const double2 md13 = make_double2(d13.y, -d13.x);  // -i (x1 - x3)
@@ -229,8 +394,8 @@ __device__ inline void fft_wave(double2 *z, int N, const TwSplit &twf, int lane)
   int M = N;
   for (; M >= 16; M >>= 4) {
     const int S = M >> 4, lS = __builtin_ctz(S);
-    if (lane < (N >> 4)) {
-      const int jj = lane & (S - 1), g = (lane >> lS) * M;
+    for (int bf = lane; bf < (N >> 4); bf += 64) {  // one butterfly per lane (two at N = 2048)
+      const int jj = bf & (S - 1), g = (bf >> lS) * M;
       double2 a[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) a[r] = z[padc(g + jj + r * S)];
@@ -249,42 +414,30 @@ __device__ inline void fft_wave(double2 *z, int N, const TwSplit &twf, int lane)
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the next pass reads other lanes' writes
   }
   if (M == 8) {  // radix 2 over blocks of 8 (S = 4), then radix 4 below
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int b = lane + 64 * q;
-      if (b < (N >> 1)) {
-        const int jj = b & 3, g = (b >> 2) * 8;
-        const double2 a0 = z[padc(g + jj)], a1 = z[padc(g + jj + 4)];
-        z[padc(g + jj)] = cadd(a0, a1);
-        z[padc(g + jj + 4)] = cmul(csub(a0, a1), twf(jj * (N / 8)));
-      }
+    for (int b = lane; b < (N >> 1); b += 64) {
+      const int jj = b & 3, g = (b >> 2) * 8;
+      const double2 a0 = z[padc(g + jj)], a1 = z[padc(g + jj + 4)];
+      z[padc(g + jj)] = cadd(a0, a1);
+      z[padc(g + jj + 4)] = cmul(csub(a0, a1), twf(jj * (N / 8)));
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     M = 4;
   }
   if (M == 4) {  // radix 4 over blocks of 4 (S = 1: no twiddles)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int b = lane + 64 * q;
-      if (b < (N >> 2)) {
-        double2 a0 = z[padc(4 * b)], a1 = z[padc(4 * b + 1)], a2 = z[padc(4 * b + 2)], a3 = z[padc(4 * b + 3)];
-        dft4(a0, a1, a2, a3);
-        z[padc(4 * b)] = a0;
-        z[padc(4 * b + 1)] = a1;
-        z[padc(4 * b + 2)] = a2;
-        z[padc(4 * b + 3)] = a3;
-      }
+    for (int b = lane; b < (N >> 2); b += 64) {
+      double2 a0 = z[padc(4 * b)], a1 = z[padc(4 * b + 1)], a2 = z[padc(4 * b + 2)], a3 = z[padc(4 * b + 3)];
+      dft4(a0, a1, a2, a3);
+      z[padc(4 * b)] = a0;
+      z[padc(4 * b + 1)] = a1;
+      z[padc(4 * b + 2)] = a2;
+      z[padc(4 * b + 3)] = a3;
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   } else if (M == 2) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int b = lane + 64 * q;
-      if (b < (N >> 1)) {
-        const double2 a0 = z[padc(2 * b)], a1 = z[padc(2 * b + 1)];
-        z[padc(2 * b)] = cadd(a0, a1);
-        z[padc(2 * b + 1)] = csub(a0, a1);
-      }
+    for (int b = lane; b < (N >> 1); b += 64) {
+      const double2 a0 = z[padc(2 * b)], a1 = z[padc(2 * b + 1)];
+      z[padc(2 * b)] = cadd(a0, a1);
+      z[padc(2 * b + 1)] = csub(a0, a1);
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   }
@@ -563,8 +716,75 @@ hipError_t launch_sketch_dense(int64_t m, int64_t n, const void *A, int dtype, i
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Explicit projection (s > kLdsMaxS: the row's s buckets no longer fit in LDS).
+// Y = A Omega^T with Omega^T = S^T diag(d) T R formed as an n x l matrix:
+// column j of A reaches coordinate q through its one bucket, so
+//   Omega^T[j, q] = sgn'(j) T[h(j), sel[q]],
+// sgn'(j) the SEM sign folded with d (the column code), and T's entry from
+// the real Fourier basis (f = sel[q], N = s/2, k = (a h + o) mod s):
+//   f = 0: 1/sqrt s;  f = N: cos(pi h)/sqrt s;
+//   0 < f < N: sqrt(2/s) cos(2 pi f h / s);
+//   f > N: -sqrt(2/s) sin(2 pi (s - f) h / s) = -sqrt(2/s) cos(2 pi ((s - f) h + 3s/4) / s),
+// or (-1)^popcount(h & f) / sqrt s for the Walsh-Hadamard form.  The product
+// is the same linear map as the transform route, summed in another order.
+// ---------------------------------------------------------------------------
+__global__ void k_cos_table(int s, const double2 *__restrict__ twp, double *__restrict__ ctab) {
+  const int N = s >> 1;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < s; k += gridDim.x * blockDim.x)
+    ctab[k] = k < N ? twp[k].x : -twp[k - N].x;
+}
+
+hipError_t launch_cos_table(int s, const double2 *twp, double *ctab, hipStream_t st) {
+  const int blocks = std::max(1, std::min(1024, (s + 255) / 256));
+  hipLaunchKernelGGL(k_cos_table, dim3(blocks), dim3(256), 0, st, s, twp, ctab);
+  return hipGetLastError();
+}
+
+__global__ void k_explicit_projection(int64_t n, int s, int l, const uint32_t *__restrict__ code,
+                                      const int32_t *__restrict__ sel, const double *__restrict__ ctab,
+                                      int hadamard, double *__restrict__ OmT) {
+  const int N = s >> 1;
+  const double rs = 1.0 / sqrt((double)s), r2s = sqrt(2.0) * rs;
+  const uint32_t mask = (uint32_t)s - 1u;
+  const int64_t total = n * (int64_t)l;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / l;
+    const int q = (int)(e - j * l);
+    const uint32_t c = code[j], h = code_bucket(c);
+    const uint32_t f = (uint32_t)sel[q];
+    double v;
+    if (hadamard) {
+      v = (__popc(h & f) & 1) ? -rs : rs;
+    } else if (f == 0) {
+      v = rs;
+    } else if (f == (uint32_t)N) {
+      v = (h & 1) ? -rs : rs;
+    } else if (f < (uint32_t)N) {
+      v = r2s * ctab[(f * h) & mask];
+    } else {
+      v = -r2s * ctab[(((uint32_t)s - f) * h + 3u * ((uint32_t)s >> 2)) & mask];
+    }
+    OmT[e] = code_apply(c, v);
+  }
+}
+
+hipError_t launch_explicit_projection(int64_t n, int s, int l, const uint32_t *code, const int32_t *sel,
+                                      const double *ctab, bool hadamard, double *OmT, hipStream_t st) {
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(8192, ceil_div(n * (int64_t)l, 256)));
+  hipLaunchKernelGGL(k_explicit_projection, dim3(blocks), dim3(256), 0, st, n, s, l, code, sel, ctab,
+                     hadamard ? 1 : 0, OmT);
+  return hipGetLastError();
+}
+
 void sketch_dense_set_attrs() {
-  const int bytes = (int)sketch_lds_bytes(kMaxS, 1024);  // l <= 1024 (validated far below)
+  const int bytes = (int)sketch_lds_bytes(kLdsMaxS, 1024);  // l <= 1024 (validated far below)
+  hipFuncSetAttribute((const void *)k_sketch_ordered<double>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  hipFuncSetAttribute((const void *)k_sketch_ordered<float>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  hipFuncSetAttribute((const void *)k_ordered_tables, hipFuncAttributeMaxDynamicSharedMemorySize, kOrdMaxChunk * 4);
+  const int ws_bytes = (int)sketch_ws_lds_bytes(2 * kWsMaxN, 1024);
+  hipFuncSetAttribute((const void *)k_sketch_ws<double>, hipFuncAttributeMaxDynamicSharedMemorySize, ws_bytes);
+  hipFuncSetAttribute((const void *)k_sketch_ws<float>, hipFuncAttributeMaxDynamicSharedMemorySize, ws_bytes);
 #define RLU_ATTR(T, P) \
   hipFuncSetAttribute((const void *)k_sketch_dense<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   RLU_ATTR(double, 4) RLU_ATTR(double, 8) RLU_ATTR(double, 16)

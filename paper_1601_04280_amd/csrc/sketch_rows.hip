@@ -23,11 +23,12 @@ constexpr int kTile = 64;  // buckets and columns of one gather tile
 // index `list`, whose entries are a position i with bit 31 set when
 // sgn_2(i) = -1.  Also the codes of the transform step: code2[j] = j with
 // bit 31 set when d_2(j) = -1.  One block; counts, then offsets, then
-// placement (in any order within a bucket), all in LDS.
+// placement (in any order within a bucket), all in LDS; with `ordered`, each
+// list is then sorted by position (insertion sort, one thread per bucket).
 __global__ void __launch_bounds__(kListThreads) k_omega2_lists(int64_t m, int l2, int log2l2, uint64_t key_sem,
                                                                uint64_t key_signs, int32_t *__restrict__ start,
                                                                uint32_t *__restrict__ list,
-                                                               uint32_t *__restrict__ code2) {
+                                                               uint32_t *__restrict__ code2, int ordered) {
   extern __shared__ uint32_t cnt[];  // l2 counters, then kListThreads / 64 wave totals
   uint32_t *wsum = cnt + l2;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -70,6 +71,20 @@ __global__ void __launch_bounds__(kListThreads) k_omega2_lists(int64_t m, int l2
     const uint32_t slot = atomicAdd(&cnt[(uint32_t)(r >> (64 - log2l2))], 1u);
     list[slot] = (uint32_t)i | ((uint32_t)(r & 1u) << 31);
   }
+  if (!ordered) return;
+  __syncthreads();  // every entry placed (and visible to the block) before the sort
+  for (int b = tid; b < l2; b += kListThreads) {
+    const int32_t a = start[b], e = start[b + 1];
+    for (int32_t p = a + 1; p < e; ++p) {
+      const uint32_t x = list[p];
+      int32_t q = p - 1;
+      while (q >= a && (list[q] & 0x7FFFFFFFu) > (x & 0x7FFFFFFFu)) {
+        list[q + 1] = list[q];
+        --q;
+      }
+      list[q + 1] = x;
+    }
+  }
 }
 
 template <typename T>
@@ -88,7 +103,11 @@ __device__ inline double load_nt(const T *p) {
 constexpr int kGatherChunk = 1024;
 constexpr int kGatherUnroll = 8;
 
-template <typename T>
+// ORD (RLU_FLAG_DETERMINISTIC, with ordered lists): wave w instead takes the
+// tile's buckets 16 w .. 16 w + 15, whose entries are one contiguous range,
+// staged 256 at a time in the wave's own quarter of the staging arrays; each
+// tile cell is then summed by one lane in list order, with plain LDS adds.
+template <typename T, bool ORD>
 __global__ void __launch_bounds__(256) k_omega2_gather(int64_t ncols, const T *__restrict__ X, int64_t ldx,
                                                         const int32_t *__restrict__ perm,
                                                         const int32_t *__restrict__ start,
@@ -107,6 +126,49 @@ __global__ void __launch_bounds__(256) k_omega2_gather(int64_t ncols, const T *_
   for (int i = tid; i < kTile * (kTile + 1); i += 256) (&tile[0][0])[i] = 0.0;
   if (tid <= nb) st_s[tid] = start[b0 + tid];
   __syncthreads();
+  if (ORD) {
+    const int bw0 = min(nb, 16 * wv), bw1 = min(nb, 16 * wv + 16);
+    const int Ea = st_s[bw0], Eb = st_s[bw1];
+    int32_t *er = ent_row + wv * (kGatherChunk / 4);
+    uint8_t *em = ent_meta + wv * (kGatherChunk / 4);
+    for (int cb = Ea; cb < Eb; cb += kGatherChunk / 4) {
+      const int ce = min(kGatherChunk / 4, Eb - cb);
+      for (int t = lane; t < ce; t += 64) {
+        const uint32_t c = list[cb + t];
+        er[t] = perm[c & 0x7FFFFFFFu];
+        int lo = bw0, hi = bw1 - 1;  // the last bb with st_s[bb] <= cb + t
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (st_s[mid] <= cb + t) lo = mid; else hi = mid - 1;
+        }
+        em[t] = (uint8_t)(lo | ((c >> 31) << 7));
+      }
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the wave's LDS operations complete in order
+      for (int e = 0; e < ce; e += kGatherUnroll) {
+        double v[kGatherUnroll];
+#pragma unroll
+        for (int u = 0; u < kGatherUnroll; ++u) {
+          const int eu = min(e + u, ce - 1);
+          v[u] = cok ? load_nt(xc + (int64_t)er[eu] * ldx) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherUnroll; ++u) {
+          if (e + u < ce) {
+            const uint8_t mt = em[e + u];
+            tile[mt & 0x7F][lane] += (mt >> 7) ? -v[u] : v[u];
+          }
+        }
+      }
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // read before the next staging overwrites
+    }
+    __syncthreads();
+    const int64_t bo = b0 + lane;
+    if (lane < nb) {
+      for (int c = wv; c < kTile; c += 4)
+        if (c0 + c < ncols) Z0T[(c0 + c) * ldz + bo] = tile[lane][c];
+    }
+    return;
+  }
   const int E0 = st_s[0], E1 = st_s[nb];
   for (int cb = E0; cb < E1; cb += kGatherChunk) {
     const int ce = min(kGatherChunk, E1 - cb);
@@ -168,25 +230,29 @@ hipError_t launch_omega2_rowcodes(int64_t m, int l2, uint64_t seed, const int32_
 }
 
 hipError_t launch_omega2_lists(int64_t m, int l2, uint64_t seed, int32_t *start, uint32_t *list,
-                               uint32_t *code2, hipStream_t st) {
+                               uint32_t *code2, bool ordered, hipStream_t st) {
   if (m < 1 || m > INT32_MAX || l2 < 2 || l2 > kMaxS || (l2 & (l2 - 1))) return hipErrorInvalidValue;
   const size_t lds = ((size_t)l2 + kListThreads / 64) * sizeof(uint32_t);
   hipLaunchKernelGGL(k_omega2_lists, dim3(1), dim3(kListThreads), lds, st, m, l2, ilog2_exact(l2),
-                     stream_key(seed, kStreamSem2), stream_key(seed, kStreamSigns2), start, list, code2);
+                     stream_key(seed, kStreamSem2), stream_key(seed, kStreamSigns2), start, list, code2,
+                     ordered ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_omega2_gather(int64_t ncols, const void *X, int dtype, int64_t ldx, const int32_t *perm,
                                 const int32_t *start, const uint32_t *list, int l2, double *Z0T, int64_t ldz,
-                                hipStream_t st) {
+                                bool ordered, hipStream_t st) {
   if (ncols < 1 || l2 < 1 || ldz < l2 || ldx < ncols) return hipErrorInvalidValue;
   const dim3 grid((unsigned)ceil_div(ncols, kTile), (unsigned)ceil_div(l2, kTile));
-  if (dtype == RLU_F64)
-    hipLaunchKernelGGL(k_omega2_gather<double>, grid, dim3(256), 0, st, ncols, (const double *)X, ldx, perm, start,
-                       list, l2, Z0T, ldz);
-  else
-    hipLaunchKernelGGL(k_omega2_gather<float>, grid, dim3(256), 0, st, ncols, (const float *)X, ldx, perm, start,
-                       list, l2, Z0T, ldz);
+#define RLU_GATHER(T, O)                                                                                      \
+  hipLaunchKernelGGL((k_omega2_gather<T, O>), grid, dim3(256), 0, st, ncols, (const T *)X, ldx, perm, start, \
+                     list, l2, Z0T, ldz)
+  if (dtype == RLU_F64) {
+    if (ordered) RLU_GATHER(double, true); else RLU_GATHER(double, false);
+  } else {
+    if (ordered) RLU_GATHER(float, true); else RLU_GATHER(float, false);
+  }
+#undef RLU_GATHER
   return hipGetLastError();
 }
 

@@ -53,8 +53,8 @@ int main(void) {
          sizeof(rlu_matrix), sizeof(rlu_params), sizeof(rlu_info), sizeof(rlu_factors));
   F(rlu_matrix, values); F(rlu_matrix, ld); F(rlu_matrix, nnz);
   F(rlu_params, seed); F(rlu_params, flags); F(rlu_params, k2); F(rlu_params, l2);
-  F(rlu_factors, perm_r); F(rlu_factors, Y); F(rlu_factors, info);
-  F(rlu_info, bad_index); F(rlu_info, min_gap_y); F(rlu_info, min_gap_b);
+  F(rlu_factors, perm_r); F(rlu_factors, Y); F(rlu_factors, ysel); F(rlu_factors, info);
+  F(rlu_info, bad_index); F(rlu_info, zero_pivots_sel); F(rlu_info, min_gap_y); F(rlu_info, min_gap_b);
   return 0;
 }
 """)
@@ -73,8 +73,10 @@ int main(void) {
     assert int(got["rlu_params.flags"]) == rlu.Params.flags.offset
     assert int(got["rlu_factors.perm_r"]) == rlu.Factors.perm_r.offset
     assert int(got["rlu_factors.Y"]) == rlu.Factors.Y.offset
+    assert int(got["rlu_factors.ysel"]) == rlu.Factors.ysel.offset
     assert int(got["rlu_factors.info"]) == rlu.Factors.info.offset
     assert int(got["rlu_info.bad_index"]) == rlu.Info.bad_index.offset
+    assert int(got["rlu_info.zero_pivots_sel"]) == rlu.Info.zero_pivots_sel.offset
     assert int(got["rlu_info.min_gap_y"]) == rlu.Info.min_gap_y.offset
     assert int(got["rlu_info.min_gap_b"]) == rlu.Info.min_gap_b.offset
     assert rlu.INFO_WORDS * 4 == int(got["rlu_info"])
@@ -98,3 +100,25 @@ def test_errors_are_reported_without_a_device():
     p = rlu.Params(2, 4, 8, 0, 1, 0, 6, 16, 0)   # valid (without a device the call may still fail)
     assert lib.rlu_sketch_params(ctypes.byref(p), 16, None, None, None, None, None) != rlu.RLU_ERR_INVALID_ARG
     assert lib.rlu_create(0, None) == rlu.RLU_ERR_INVALID_ARG
+
+
+def test_parameter_ranges_without_a_device():
+    """s in [2, 65536] (powers of two), l <= 1024, l2 <= 8192, the flag bits:
+    rejected or let through by the host-side validation alone."""
+    lib = rlu.load_library()
+
+    def status(k, l, s, flags=0, k2=0, l2=0):
+        p = rlu.Params(k, l, s, 0, 1, flags, k2, l2, 0)
+        return lib.rlu_sketch_params(ctypes.byref(p), 2048, None, None, None, None, None)
+
+    bad = rlu.RLU_ERR_INVALID_ARG
+    assert status(4, 8, 131072) == bad and b"65536" in lib.rlu_last_error()
+    assert status(4, 8, 1) == bad
+    assert status(4, 8, 65536) != bad
+    assert status(4, 1024, 2048) != bad
+    assert status(4, 1025, 2048) == bad and b"1024" in lib.rlu_last_error()
+    assert status(4, 8, 16, k2=16, l2=16384) == bad and b"l2" in lib.rlu_last_error()
+    assert status(4, 8, 16, k2=16, l2=8192) != bad
+    assert status(4, 8, 16, flags=rlu.RLU_FLAG_DETERMINISTIC | rlu.RLU_FLAG_HADAMARD) != bad
+    assert status(4, 8, 16, flags=rlu.RLU_FLAG_TRUNCATE) != bad
+    assert status(4, 8, 16, flags=128) == bad and b"flag" in lib.rlu_last_error()

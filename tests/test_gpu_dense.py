@@ -61,6 +61,9 @@ def test_params_bit_exact(n, l, s, seed):
     (80, 96, 20, 32, 27, np.float64),         # 16
     (500, 2048, 100, 2048, 28, np.float32),   # FP32 storage, 16-byte loads
     (9000, 6148, 120, 1024, 29, np.float32),  # FP32, ragged chunk, counter tail
+    # s = 4096 on the wave-specialised path (two butterflies per lane, 16 16 8)
+    (2000, 16384, 520, 4096, 30, np.float32),  # the 32768 x 16384 workload's row shape
+    (700, 4100, 300, 4096, 31, np.float64),    # FP64, ragged chunk
 ])
 def test_sketch_matches_oracle(m, n, l, s, seed, dtype):
     a = np.random.default_rng(seed).standard_normal((m, n)).astype(dtype)
@@ -79,9 +82,10 @@ def test_sketch_matches_oracle(m, n, l, s, seed, dtype):
     (50, 64, 12, 16, 35, np.float64),         # 4
     (50, 40, 6, 8, 36, np.float64),           # 3
     (500, 2048, 100, 2048, 37, np.float32),   # FP32 storage
+    (600, 8192, 520, 4096, 43, np.float32),   # 12 stages: 4 4 4 at s = 4096
     # one block per row (other shapes)
     (200, 8192, 100, 8192, 38, np.float64),   # 13 stages: 4 4 4 1
-    (300, 2049, 64, 4096, 39, np.float64),    # ragged row length
+    (300, 2049, 64, 4096, 39, np.float64),    # row length not a multiple of the vector width
     (64, 300, 2, 2, 40, np.float64),          # s = 2
     (64, 300, 3, 4, 41, np.float64),          # s = 4
     (200, 777, 40, 128, 42, np.float32),
@@ -298,7 +302,7 @@ def test_nonfinite_input_reports_numeric():
 
 
 @pytest.mark.parametrize("kw", [dict(k=5, l=4, s=8), dict(k=2, l=9, s=8), dict(k=2, l=4, s=12),
-                                dict(k=2, l=70, s=128), dict(k=2, l=4, s=16384)])
+                                dict(k=2, l=70, s=128), dict(k=2, l=4, s=131072)])
 def test_invalid_arguments(kw):
     A = to_dev(np.ones((60, 50)))
     with pytest.raises(rlu.RluError) as e:
@@ -319,8 +323,8 @@ def test_workspace_too_small():
     pc = torch.empty(50, dtype=torch.int32, device=DEV)
     info = rlu.alloc_info(DEV)
     ws = torch.empty(1024, dtype=torch.uint8, device=DEV)
-    f = rlu.Factors(L.data_ptr(), 4, U.data_ptr(), 50, pr.data_ptr(), pc.data_ptr(), None, None, None, 0,
-                    None, None, info.data_ptr())
+    f = rlu.Factors(L=L.data_ptr(), ldl=4, U=U.data_ptr(), ldu=50, perm_r=pr.data_ptr(), perm_c=pc.data_ptr(),
+                    info=info.data_ptr())
     st = lib.rlu_factor(ctx.handle, ctypes.byref(mat), ctypes.byref(p), ctypes.byref(f), ws.data_ptr(), 1024,
                         None)
     assert st == rlu.RLU_ERR_NO_MEMORY

@@ -138,19 +138,20 @@ def test_second_projection_invalid_arguments(kw):
         rlu.factor(A, k=4, l=32, s=64, seed=1, **kw)
 
 
-def test_second_projection_rejects_reduced_precision_and_wide_csr():
+def test_second_projection_rejects_reduced_precision_and_too_many_rows():
     A = to_dev(np.random.default_rng(0).standard_normal((300, 200)))
     with pytest.raises(rlu.RluError):
         rlu.factor(A, k=4, l=8, s=16, seed=1, precision="bf16", k2=32, l2=64)
     rp, col, val = synth.random_csr(300, 200, 0.05, 1)[:3]
     csr = (torch.from_numpy(rp).to(DEV), torch.from_numpy(col).to(DEV), torch.from_numpy(val).to(DEV), 300, 200)
-    with pytest.raises(rlu.RluError):  # the CSR kernel keeps at most 576 outputs
-        rlu.factor(csr=csr, k=4, l=8, s=16, seed=1, k2=600, l2=1024)
+    with pytest.raises(rlu.RluError):  # the transform kernels keep at most 1024 outputs per row
+        rlu.factor(csr=csr, k=4, l=8, s=16, seed=1, k2=1100, l2=2048)
 
 
 @pytest.mark.parametrize("m,n,k,l,s,k2,l2,density", [(3000, 2000, 20, 30, 256, 96, 512, 0.01),
                                                      (1500, 2500, 40, 70, 512, 200, 1024, 0.02),
-                                                     (900, 700, 10, 16, 64, 64, 128, 0.05)])
+                                                     (900, 700, 10, 16, 64, 64, 128, 0.05),
+                                                     (2000, 1500, 20, 30, 256, 600, 1024, 0.02)])  # 12 outputs per lane
 @pytest.mark.parametrize("transform", ["fourier", "hadamard"])
 def test_second_projection_csr_matches_oracle(m, n, k, l, s, k2, l2, density, transform):
     # Omega_2 P A through the CSR sketch of a CSC copy of A

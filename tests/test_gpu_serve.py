@@ -168,3 +168,36 @@ def test_served_requests_match_oracle():
             assert abs(r_g - r_o) <= 1e-3 * r_o
         else:
             assert r_g <= 1e-4
+
+
+@pytest.mark.parametrize("max_inflight", [1, 4])
+def test_exclusive_slot_graphs(max_inflight):
+    """With one slot, requests run one at a time with the device to
+    themselves: ordinary panel launches, each request launched as a captured
+    graph, updated in place for repeated topologies.  The results equal
+    rlu_factor's (bit for bit in deterministic mode with one slot, which
+    plans like rlu_factor), and repeat bit for bit."""
+    shapes = [(1500, 700, 16, 128), (900, 1100, 32, 256), (1500, 700, 16, 128), (3000, 400, 64, 256),
+              (900, 1100, 32, 256), (1500, 700, 16, 128)]
+    fl = rlu.RLU_FLAG_DETERMINISTIC
+    mats = [to_dev(synth.lowrank_dense(m, n, synth.spectrum_geometric(20), 700 + i, noise=1e-10))
+            for i, (m, n, k, s) in enumerate(shapes)]
+    direct = [rlu.factor(A, k=k, l=k + 10, s=s, seed=9, flags=fl, keep_intermediates=True)
+              for A, (m, n, k, s) in zip(mats, shapes)]
+    torch.cuda.synchronize()
+    with rlu.Server(hbm_budget_bytes=1 << 30, max_inflight=max_inflight) as srv:
+        outs = []
+        for rep in range(3):   # later rounds reuse the slot's graphs
+            tickets = [srv.submit(A, k=k, l=k + 10, s=s, seed=9, flags=fl, keep_intermediates=True)
+                       for A, (m, n, k, s) in zip(mats, shapes)]
+            outs.append([srv.wait(t) for t in tickets])
+        st = srv.stats()
+    print(f"max_inflight {max_inflight}: {st}")
+    assert st["exclusive_slot"] == (max_inflight == 1)
+    if st["exclusive_slot"]:
+        assert st["graph_launches"] + st["direct_fallbacks"] == 3 * len(shapes)
+        assert st["graph_launches"] > 0
+    for rnd in outs:
+        for g, d in zip(rnd, direct):
+            for key in ["L", "U", "perm_r", "perm_c", "Y", "B"]:
+                assert torch.equal(getattr(g, key), getattr(d, key)), key
