@@ -64,7 +64,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="dense_16384x8192_invsq", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", choices=["f64", "f32", "bf16"], default=None)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip every oracle run: the CPU baseline, the headline parity key and the forms' oracle errors")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--extras", default=",".join(EXTRAS),
                     help="comma-separated blocks to add to the line (default: all of %s)" % ", ".join(EXTRAS))
@@ -273,19 +274,53 @@ def parity_block(rlu, A_dev, w, ctx, o):
     return res
 
 
-def forms_block(rlu, ctx, dev):
+def unpermuted_product(L, U, perm_r, perm_c):
+    """P^T (L U) Q^T: the approximation of A in A's own row and column order."""
+    import torch
+    D = torch.empty(L.shape[0], U.shape[1], dtype=torch.float64, device=L.device)
+    D[perm_r.long().unsqueeze(1), perm_c.long().unsqueeze(0)] = L @ U
+    return D
+
+
+def forms_block(rlu, ctx, dev, with_oracle=True):
     import torch
     name = "dense_32768x16384_exp_fp32"
     w = WORKLOADS[name]
     A = make_input(name, dev)
     torch.cuda.synchronize()
     res = {"workload": name, "m": w["m"], "n": w["n"], "k": w["k"], "l": w["l"], "s": w["s"], "storage": "float32"}
+    oracle = None
+    if with_oracle:   # the FP64 oracle on the same matrix and seed, for the error of every form
+        import numpy as np
+        from oracle import rlu as R
+        t0 = time.perf_counter()
+        A64h = A.cpu().numpy().astype(np.float64)
+        o = R.rlu(A64h, R.Params(w["k"], w["l"], w["s"], SEED))
+        del A64h
+        oracle = {"perm_r": o.perm_r, "perm_c": o.perm_c,
+                  "LU": unpermuted_product(torch.from_numpy(o.L).to(dev), torch.from_numpy(o.U).to(dev),
+                                           torch.from_numpy(o.perm_r).to(dev), torch.from_numpy(o.perm_c).to(dev))}
+        oracle["rel_residual"] = (torch.linalg.norm(oracle["LU"] - A.double()) / torch.linalg.norm(A.double())).item()
+        res["oracle"] = {"seconds": round(time.perf_counter() - t0, 1), "rel_residual": oracle["rel_residual"],
+                         "min_gap_y": float(o.min_gap_y), "min_gap_b": float(o.min_gap_b)}
+        del o
+        print(f"# forms: oracle in {res['oracle']['seconds']} s", file=sys.stderr, flush=True)
     for prec in ("f64", "f32", "bf16"):
         ms, per, out = run(rlu, A, w, prec, steps=5, warmup=1, ctx=ctx)
         res[prec] = {"ms_per_step": round(ms, 3), "decomps_per_s": round(1e3 / ms, 3),
                      "rel_residual": rel_residual(A, out),
                      "contract": contract_rate(w, per, prec),
                      "stages_ms": {k: round(v, 4) for k, v in per.items()}}
+        if oracle is not None:   # the error of this result against the FP64 oracle
+            import numpy as np
+            a_fro = torch.linalg.norm(A.double()).item()
+            LUg = unpermuted_product(out.L, out.U, out.perm_r.long(), out.perm_c.long())
+            res[prec]["vs_oracle"] = {
+                "perm_r_identical": bool(np.array_equal(out.perm_r.cpu().numpy(), oracle["perm_r"])),
+                "perm_c_identical": bool(np.array_equal(out.perm_c.cpu().numpy(), oracle["perm_c"])),
+                "lu_rel_diff": (torch.linalg.norm(LUg - oracle["LU"]) / a_fro).item(),
+                "residual_rel_diff": abs(res[prec]["rel_residual"] - oracle["rel_residual"]) / oracle["rel_residual"]}
+            del LUg
         del out
         print(f"# forms {prec}: {ms:.2f} ms/step, residual {res[prec]['rel_residual']:.6e}", file=sys.stderr,
               flush=True)
@@ -476,6 +511,7 @@ def serve_block(rlu, dev, counts=(600, 2000, 600), fracs=(0.5, 0.7, 0.9), n_sat=
                             "decomps_per_s": round(count / wall, 2)})
         print(f"# serving {frac:.1f} x saturated ({rate:.0f}/s): p50 {res['runs'][-1]['p50_ms']} ms, "
               f"p99 {res['runs'][-1]['p99_ms']} ms", file=sys.stderr, flush=True)
+    res["loop"] = srv.stats()
     srv.stop()
     bad = int((torch.stack(infos)[:, 0] != 0).sum().item())
     if bad:
@@ -579,11 +615,14 @@ def main():
     del A
     torch.cuda.empty_cache()
     if "forms" in extras:
-        line["forms"] = forms_block(rlu, ctx, dev)
+        line["forms"] = forms_block(rlu, ctx, dev, with_oracle=not args.no_cpu_baseline)
     if "csr" in extras:
         line["csr"] = csr_block(rlu, ctx, dev)
     if "serving" in extras:
         line["serving"] = serve_block(rlu, dev)
+        # one slot: requests one at a time with the device to themselves,
+        # launched as captured graphs (rlu_serve_stats)
+        line["serving"]["one_slot"] = serve_block(rlu, dev, counts=(600,), fracs=(0.7,), n_sat=300, max_inflight=1)
     if "accuracy" in extras:
         line["accuracy"] = accuracy_block(rlu, ctx, dev)
     # release the library's streams and events while the runtime is whole
