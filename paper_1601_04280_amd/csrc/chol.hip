@@ -4,16 +4,10 @@
 // (Corollary 3.2's product through the normal equations).  With
 // G = Lhat^T Lhat = L L^T, G^{-1} = L^{-T} L^{-1}.
 //
-// k_chol: one block of 8 waves, G (l x l, lower part) in global memory
-//   (L2-resident), right-looking over 16-column panels j0:
-//   1. wave 0 factors the 16 x 16 diagonal block, one row per lane, and
-//      inverts it through LDS (D = L11^{-1}, kept for k_trinv);
-//   2. every thread solves rows of the panel below it, L21 = G21 L11^{-T}
-//      (row r: L21[r][c] = sum_{c' <= c} G21[r][c'] D[c][c']), into G and LDS;
-//   3. the waves update the lower 16 x 16 tiles of the trailing matrix,
-//      G22 -= L21 L21^T, with v_mfma_f64_16x16x4_f64 (K = 16: four steps),
-//      eight tiles per wave per round trip to L2.
-//   Four barriers per panel.
+// k_chol_reg (l <= 256, or one diagonal panel of a larger G): one block of
+//   8 waves with the lower tile triangle in registers, right-looking over
+//   16-column panels (details at the kernel).  Larger l: panels of at most
+//   256 columns chained through the FP64 GEMM (launch_chol_inv).
 // k_trinv: one block per column c of L^{-1}; blocked forward substitution
 //   x[I] = D_I (e_c[I] - L[I][0:i0] x[0:i0]) over the 16-row blocks I.
 // A non-positive pivot (G numerically singular) sets RLU_ERR_NUMERIC.
@@ -24,146 +18,9 @@ namespace rlu {
 
 typedef double v4d_c __attribute__((ext_vector_type(4)));
 
-constexpr int kCT = 512;  // threads of k_chol
+constexpr int kCT = 512;  // threads of k_chol_reg
 constexpr int kCNB = 16;   // panel width
 constexpr int kPS = kCNB + 1;
-constexpr int kTG = 8;     // trailing tiles per wave per round trip
-
-__global__ __launch_bounds__(kCT) void k_chol(int l, double *__restrict__ G, double *__restrict__ Dinv,
-                                              rlu_info *info) {
-  extern __shared__ double P[];  // rows below the diagonal block x 16 (stride kPS): the panel's L21
-  __shared__ double D[kCNB][kCNB];
-  __shared__ double L11s[kCNB][kCNB + 1];
-  __shared__ int s_bad;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) s_bad = 0;
-
-  for (int j0 = 0; j0 < l; j0 += kCNB) {
-    const int nb = min(kCNB, l - j0);
-    const int j1 = j0 + nb, t = l - j1;
-    // 1. diagonal block: lane r holds row r of G[j0:j1, j0:j1] (lower part);
-    //    the factor goes to G and to L11s (identity rows / columns past nb)
-    if (wave == 0) {
-      double a[kCNB];
-      const int r = lane;
-#pragma unroll
-      for (int c = 0; c < kCNB; ++c) a[c] = (r < nb && c <= r && c < nb) ? G[(int64_t)(j0 + r) * l + j0 + c] : 0.0;
-      int bad = 0;
-#pragma unroll
-      for (int c = 0; c < kCNB; ++c) {
-        if (c < nb) {
-          double d = __shfl(a[c], c, 64);  // pivot: row c, column c
-          if (!(d > 0.0)) {
-            bad = 1;
-            d = 1.0;
-          }
-          const double sq = sqrt(d);
-          if (r == c) a[c] = sq;
-          else if (r > c) a[c] /= sq;
-          // update of the columns right of c: a[r][c'] -= a[r][c] * a[c'][c]
-#pragma unroll
-          for (int cp = c + 1; cp < kCNB; ++cp) {
-            const double lc = __shfl(a[c], cp, 64);  // row cp, column c
-            if (r >= cp) a[cp] -= a[c] * lc;
-          }
-        }
-      }
-      if (bad && lane == 0) s_bad = 1;
-      if (r < kCNB) {
-#pragma unroll
-        for (int c = 0; c < kCNB; ++c) {
-          const double v = (c <= r) ? a[c] : 0.0;
-          L11s[r][c] = (r < nb) ? v : (r == c ? 1.0 : 0.0);
-          if (r < nb && c < nb) G[(int64_t)(j0 + r) * l + j0 + c] = v;
-        }
-      }
-    }
-    __syncthreads();
-    if (wave == 0 && lane < kCNB) {  // column `lane` of L11^{-1} by forward substitution
-      const int r = lane;
-      double x[kCNB];
-#pragma unroll
-      for (int i = 0; i < kCNB; ++i) {
-        double sum = (i == r) ? 1.0 : 0.0;
-#pragma unroll
-        for (int u = 0; u < i; ++u) sum -= L11s[i][u] * x[u];
-        x[i] = (i >= r) ? sum / L11s[i][i] : 0.0;
-      }
-#pragma unroll
-      for (int i = 0; i < kCNB; ++i) D[i][r] = (i < nb && r < nb) ? x[i] : 0.0;
-    }
-    __syncthreads();
-    double *dblk = Dinv + (size_t)(j0 / kCNB) * kCNB * kCNB;
-    if (tid < kCNB * kCNB) dblk[tid] = D[tid / kCNB][tid % kCNB];
-
-    // 2. L21 = G21 L11^{-T}
-    for (int rr = tid; rr < t; rr += kCT) {
-      const int64_t row = j1 + rr;
-      double g[kCNB];
-#pragma unroll
-      for (int c = 0; c < kCNB; ++c) g[c] = c < nb ? G[row * l + j0 + c] : 0.0;
-#pragma unroll
-      for (int c = 0; c < kCNB; ++c) {
-        double s = 0.0;
-#pragma unroll
-        for (int cp = 0; cp <= c; ++cp) s += g[cp] * D[c][cp];
-        P[rr * kPS + c] = s;
-        if (c < nb) G[row * l + j0 + c] = s;
-        __builtin_amdgcn_sched_barrier(0);  // keep D's reads per column: no hoisting of all 136
-      }
-    }
-    __syncthreads();
-
-    // 3. trailing update of the lower tiles: G22 -= L21 L21^T.  Each wave takes
-    //    groups of kTG tiles: all their loads first, then the MFMAs, then the
-    //    stores, so one L2 round trip is paid per group rather than per tile.
-    const int tb = (t + 15) / 16;
-    const int ntiles = tb * (tb + 1) / 2;
-    for (int q0 = wave * kTG; q0 < ntiles; q0 += (kCT / 64) * kTG) {
-      v4d_c acc[kTG];
-      int bis[kTG], bjs[kTG];
-#pragma unroll
-      for (int g = 0; g < kTG; ++g) {
-        const int q = min(q0 + g, ntiles - 1);  // past the end: a copy of the last tile, not stored
-        int bi = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
-        while ((bi + 1) * (bi + 2) / 2 <= q) ++bi;
-        while (bi * (bi + 1) / 2 > q) --bi;
-        bis[g] = bi;
-        bjs[g] = q - bi * (bi + 1) / 2;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = bis[g] * 16 + (lane >> 4) + 4 * v, j = bjs[g] * 16 + (lane & 15);
-          const bool ok = i < t && j < t;
-          const double c = G[(int64_t)(j1 + (ok ? i : 0)) * l + j1 + (ok ? j : 0)];
-          acc[g][v] = ok ? c : 0.0;
-        }
-      }
-#pragma unroll
-      for (int g = 0; g < kTG; ++g) {
-#pragma unroll
-        for (int kk = 0; kk < kCNB / 4; ++kk) {
-          const int k = kk * 4 + (lane >> 4);
-          const int ia = bis[g] * 16 + (lane & 15), jb = bjs[g] * 16 + (lane & 15);
-          const double av = ia < t ? -P[ia * kPS + k] : 0.0;
-          const double bv = jb < t ? P[jb * kPS + k] : 0.0;
-          acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[g], 0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int g = 0; g < kTG; ++g) {
-        if (q0 + g < ntiles) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int i = bis[g] * 16 + (lane >> 4) + 4 * v, j = bjs[g] * 16 + (lane & 15);
-            if (i < t && j < t) G[(int64_t)(j1 + i) * l + j1 + j] = acc[g][v];
-          }
-        }
-      }
-    }
-    __syncthreads();
-  }
-  if (tid == 0 && s_bad) atomicExch(&info->status, (int)RLU_ERR_NUMERIC);
-}
 
 __device__ inline double readlane_f64(double v, int src) {
   const long long b = __double_as_longlong(v);
@@ -183,8 +40,8 @@ __device__ inline double rsqrt_f64(double d) {
   return y;
 }
 
-// k_chol_reg: the same right-looking factorization for l <= 256 with the
-// whole lower tile triangle held in registers: tile q of the packed lower
+// k_chol_reg: right-looking factorization of an l x l block (l <= 256, row
+// stride ld) with the whole lower tile triangle held in registers: tile q of the packed lower
 // triangle (column-major over 16 x 16 tiles) lives in wave q % 8, slot q / 8,
 // in the MFMA accumulator layout (lane: row lane/16 + 4v, column lane%16).
 // Per panel p, with no global-memory round trip:
@@ -196,10 +53,10 @@ __device__ inline double rsqrt_f64(double d) {
 //   C. one thread per row below solves L21 = G21 L11^{-T} into P and G;
 //   D. each wave updates its trailing tiles, G22 -= L21 L21^T, by MFMA with
 //      operands read from P.
-// Three barriers per panel.  L (lower part) and the D blocks are written out
-// as in k_chol.
+// Three barriers per panel.  L (lower part) goes back to G and the 16 x 16
+// diagonal inverses D to Dinv, in panel order, for k_trinv.
 template <int TPW>
-__global__ __launch_bounds__(kCT) void k_chol_reg(int l, double *__restrict__ G, double *__restrict__ Dinv,
+__global__ __launch_bounds__(kCT) void k_chol_reg(int l, int ld, double *__restrict__ G, double *__restrict__ Dinv,
                                                   rlu_info *info) {
   extern __shared__ double P2[];  // 2 buffers x (l - 16) rows x kPS
   __shared__ double Dg[kCNB][kCNB + 1];
@@ -233,7 +90,7 @@ __global__ __launch_bounds__(kCT) void k_chol_reg(int l, double *__restrict__ G,
     for (int v = 0; v < 4; ++v) {
       const int i = bi * kCNB + (lane >> 4) + 4 * v, j = bj * kCNB + (lane & 15);
       const bool ok = q < ntiles && i < l && j < l;
-      const double c = G[(ok ? i : 0) * l + (ok ? j : 0)];  // l <= 256: 32-bit offsets
+      const double c = G[(ok ? i : 0) * ld + (ok ? j : 0)];  // l <= 256, ld <= 1024: 32-bit offsets
       acc[sl][v] = ok ? c : 0.0;
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -292,7 +149,7 @@ __global__ __launch_bounds__(kCT) void k_chol_reg(int l, double *__restrict__ G,
 #pragma unroll
         for (int c = 0; c < kCNB; ++c) L11s[r][c] = (c <= r) ? a[c] : 0.0;
         if (r < nb) {
-          double *grow = G + (int64_t)(j0 + r) * l + j0;
+          double *grow = G + (int64_t)(j0 + r) * ld + j0;
 #pragma unroll
           for (int c = 0; c < kCNB; ++c)
             if (c < nb) grow[c] = (c <= r) ? a[c] : 0.0;
@@ -323,7 +180,7 @@ __global__ __launch_bounds__(kCT) void k_chol_reg(int l, double *__restrict__ G,
       double g[kCNB];
 #pragma unroll
       for (int c = 0; c < kCNB; ++c) g[c] = P[tid * kPS + c];
-      double *grow = G + (int64_t)(j1 + tid) * l + j0;
+      double *grow = G + (int64_t)(j1 + tid) * ld + j0;
 #pragma unroll
       for (int c = 0; c < kCNB; ++c) {
         double s = 0.0;
@@ -355,8 +212,10 @@ __global__ __launch_bounds__(kCT) void k_chol_reg(int l, double *__restrict__ G,
   if (tid == 0 && s_bad) atomicExch(&info->status, (int)RLU_ERR_NUMERIC);
 }
 
-// One block per column c of L^{-1}: 16 rows per block step, 16 threads per row.
-__global__ __launch_bounds__(256) void k_trinv(int l, const double *__restrict__ L,
+// One block per column c of L^{-1} (L: l x l lower, row stride ld; the
+// result goes to Linv with the same stride): 16 rows per block step, 16
+// threads per row.
+__global__ __launch_bounds__(256) void k_trinv(int l, int ld, const double *__restrict__ L,
                                                const double *__restrict__ Dinv, double *__restrict__ Linv) {
   __shared__ double x[1024];
   __shared__ double tv[kCNB];
@@ -368,7 +227,7 @@ __global__ __launch_bounds__(256) void k_trinv(int l, const double *__restrict__
     const int nbp = min(kCNB, l - i0);
     double acc = 0.0;
     if (r < nbp)
-      for (int u = c + q; u < i0; u += 16) acc += L[(int64_t)(i0 + r) * l + u] * x[u];
+      for (int u = c + q; u < i0; u += 16) acc += L[(int64_t)(i0 + r) * ld + u] * x[u];
     acc += __shfl_xor(acc, 1, 64);
     acc += __shfl_xor(acc, 2, 64);
     acc += __shfl_xor(acc, 4, 64);
@@ -383,12 +242,34 @@ __global__ __launch_bounds__(256) void k_trinv(int l, const double *__restrict__
     }
     __syncthreads();
   }
-  for (int t = tid; t < l; t += 256) Linv[(int64_t)t * l + c] = (t >= c) ? x[t] : 0.0;
+  for (int t = tid; t < l; t += 256) Linv[(int64_t)t * ld + c] = (t >= c) ? x[t] : 0.0;
 }
 
-size_t chol_scratch_bytes(int l) { return align_up((size_t)ceil_div(l, kCNB) * kCNB * kCNB * 8, 256); }
+// Blocked form for l > 256: panels of nb <= 256 columns (equal widths,
+// multiples of 16), each factored by k_chol_reg and inverted by k_trinv in
+// place, with the panel products on the FP64 GEMM.  G is the full symmetric
+// Gram matrix; the trailing updates are applied to whole squares, so the
+// block right of a diagonal block stays the transpose of the one below it.
+// For panel p (rows and columns J = j0 .. j1 - 1, T = j1 .. l - 1):
+//   1. L_JJ = chol(G_JJ) (k_chol_reg), X_JJ = L_JJ^{-1} (k_trinv) into Linv;
+//   2. L_TJ^T = X_JJ G_JT, kept in Linv's upper part (free until the end);
+//   3. G_TT -= L_TJ L_TJ^T.
+// Then the blocks of L^{-1} below the diagonal, row panel by row panel:
+//   X_IK = -X_II (sum over panels P < I of L_IP X_PK) for the columns K < I,
+// i.e. X_I,<I = -X_II (L^T_<I,I)^T X_<I,<I, and Linv's upper part is cleared.
+static int chol_panels(int l) { return l <= 256 ? 1 : (l + 255) / 256; }
+static int chol_panel_width(int l) {
+  const int P = chol_panels(l);
+  return (int)ceil_div(ceil_div(l, P), kCNB) * kCNB;
+}
 
-typedef void (*CholRegKernel)(int, double *, double *, rlu_info *);
+size_t chol_scratch_bytes(int l) {
+  size_t b = align_up((size_t)ceil_div(l, kCNB) * kCNB * kCNB * 8, 256);
+  if (l > 256) b += align_up((size_t)chol_panel_width(l) * l * 8, 256);  // X_I,<I products
+  return b;
+}
+
+typedef void (*CholRegKernel)(int, int, double *, double *, rlu_info *);
 
 // tiles per wave for a lower tile triangle of tb x tb tiles (tb <= 16)
 static CholRegKernel chol_reg_kernel(int tb) {
@@ -401,25 +282,78 @@ static CholRegKernel chol_reg_kernel(int tb) {
   return nullptr;
 }
 
+// zeros of Linv right of the diagonal blocks (panels of nb), in columns c0 .. c1 - 1
+__global__ void k_clear_upper(int l, int nb, int c0, int c1, double *__restrict__ Linv) {
+  const int w = c1 - c0;
+  const int64_t total = (int64_t)c0 * w;  // rows above column c0's panel end at most c0
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / w), c = c0 + (int)(e - (int64_t)r * w);
+    if (c >= (r / nb + 1) * nb) Linv[(int64_t)r * l + c] = 0.0;
+  }
+}
+
+static hipError_t chol_reg_launch(int n, int ld, double *G, double *Dinv, rlu_info *info, hipStream_t st) {
+  const int tb = (n + kCNB - 1) / kCNB;
+  CholRegKernel k = chol_reg_kernel(tb);
+  if (!k) return hipErrorInvalidValue;
+  const size_t lds = (size_t)2 * std::max(1, n - kCNB) * kPS * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(1), dim3(kCT), lds, st, n, ld, G, Dinv, info);
+  return hipGetLastError();
+}
+
 hipError_t launch_chol_inv(int l, double *G, double *Linv, double *dinv_scratch, rlu_info *info,
                            hipStream_t st) {
   if (l > 1024) return hipErrorInvalidValue;
   hipError_t e;
-  const int tb = (l + kCNB - 1) / kCNB;
-  if (CholRegKernel k = tb <= 16 ? chol_reg_kernel(tb) : nullptr) {
-    const size_t lds = (size_t)2 * std::max(1, l - kCNB) * kPS * sizeof(double);
-    if ((e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
-      return e;
-    hipLaunchKernelGGL(k, dim3(1), dim3(kCT), lds, st, l, G, dinv_scratch, info);
-  } else {
-    const size_t lds = (size_t)std::max(1, l - 1) * kPS * sizeof(double);
-    if ((e = hipFuncSetAttribute((const void *)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
-      return e;
-    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCT), lds, st, l, G, dinv_scratch, info);
+  if (l <= 256) {
+    if ((e = chol_reg_launch(l, l, G, dinv_scratch, info, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_trinv, dim3(l), dim3(256), 0, st, l, l, G, dinv_scratch, Linv);
+    return hipGetLastError();
   }
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_trinv, dim3(l), dim3(256), 0, st, l, G, dinv_scratch, Linv);
-  return hipGetLastError();
+  const int nbw = chol_panel_width(l);
+  double *Tx = dinv_scratch + align_up((size_t)ceil_div(l, kCNB) * kCNB * kCNB * 8, 256) / 8;
+  auto gemm = [&](int64_t M, int64_t N, int64_t K, const double *A, bool ta, const double *B, double *C,
+                  double alpha, double beta) {
+    GemmArgs g{};
+    g.M = M; g.N = N; g.K = K;
+    g.A = A; g.lda = l; g.a_dtype = RLU_F64; g.trans_a = ta;
+    g.B = B; g.ldb = l;
+    g.C = C; g.ldc = l; g.alpha = alpha; g.beta = beta;
+    g.compute = RLU_F64;
+    return gemm_f64(g, st);
+  };
+  for (int j0 = 0; j0 < l; j0 += nbw) {
+    const int nb = std::min(nbw, l - j0), j1 = j0 + nb, t = l - j1;
+    double *Gjj = G + (int64_t)j0 * l + j0;
+    double *Xjj = Linv + (int64_t)j0 * l + j0;
+    double *dblk = dinv_scratch + (size_t)(j0 / kCNB) * kCNB * kCNB;
+    if ((e = chol_reg_launch(nb, l, Gjj, dblk, info, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_trinv, dim3(nb), dim3(256), 0, st, nb, l, Gjj, dblk, Xjj);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (t == 0) break;
+    double *LTjt = Linv + (int64_t)j0 * l + j1;  // L_TJ^T, in Linv's upper part
+    if ((e = gemm(nb, t, nb, Xjj, false, G + (int64_t)j0 * l + j1, LTjt, 1.0, 0.0)) != hipSuccess) return e;
+    if ((e = gemm(t, t, nb, LTjt, true, LTjt, G + (int64_t)j1 * l + j1, -1.0, 1.0)) != hipSuccess) return e;
+  }
+  auto clear = [&](int c0, int c1) {
+    hipLaunchKernelGGL(k_clear_upper, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div((int64_t)c0 * (c1 - c0), 256)))),
+                       dim3(256), 0, st, l, nbw, c0, c1, Linv);
+    return hipGetLastError();
+  };
+  int i0 = nbw;
+  for (; i0 < l; i0 += nbw) {
+    const int nb = std::min(nbw, l - i0);
+    // the previous column panel's L^T blocks are spent: X_<I,<I is lower triangular
+    if ((e = clear(i0 - nbw, i0)) != hipSuccess) return e;
+    // Tx (nb x i0) = (L^T_<I,I)^T X_<I,<I, then X_I,<I = -X_II Tx
+    if ((e = gemm(nb, i0, i0, Linv + i0, true, Linv, Tx, 1.0, 0.0)) != hipSuccess) return e;
+    if ((e = gemm(nb, i0, nb, Linv + (int64_t)i0 * l + i0, false, Tx, Linv + (int64_t)i0 * l, -1.0, 0.0)) !=
+        hipSuccess)
+      return e;
+  }
+  return clear(i0 - nbw, l);
 }
 
 }  // namespace rlu

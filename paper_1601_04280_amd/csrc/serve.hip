@@ -42,24 +42,46 @@ namespace rlu {
 
 constexpr int kMaxInflight = 64;
 constexpr int kMaxBypass = 8;
-constexpr int kGraphCache = 8;  // instantiated graphs kept per slot
+constexpr int kGraphCache = 16;  // instantiated graphs kept per slot
 
-// Launch topology of a request: requests with equal keys capture graphs of
-// the same shape, so an instantiated graph is first tried for them.
-struct GraphKey {
-  int64_t m, n, nnz;
-  int32_t layout, dtype, k, l, s, precision, k2, l2;
-  uint32_t flags;
-  bool operator==(const GraphKey &o) const {
-    return m == o.m && n == o.n && nnz == o.nnz && layout == o.layout && dtype == o.dtype && k == o.k &&
-           l == o.l && s == o.s && precision == o.precision && k2 == o.k2 && l2 == o.l2 && flags == o.flags;
-  }
-};
+// Launch topology of a captured request: its nodes in capture order, each as
+// (node type, kernel function).  Requests of different shapes often launch
+// the same kernel sequence with other grids and arguments, which an
+// instantiated graph takes by hipGraphExecUpdate, so the topology, not the
+// shape, is the cache key.
 struct GraphEntry {
-  GraphKey key;
+  uint64_t hash = 0;
+  std::vector<uint64_t> topo;
   hipGraphExec_t exec = nullptr;
   uint64_t last_use = 0;
 };
+
+static bool graph_topology(hipGraph_t g, std::vector<uint64_t> *topo, uint64_t *hash) {
+  size_t n = 0;
+  if (hipGraphGetNodes(g, nullptr, &n) != hipSuccess) return false;
+  std::vector<hipGraphNode_t> nodes(n);
+  if (n && hipGraphGetNodes(g, nodes.data(), &n) != hipSuccess) return false;
+  topo->assign(2 * n, 0);
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the words
+  for (size_t i = 0; i < n; ++i) {
+    hipGraphNodeType t;
+    if (hipGraphNodeGetType(nodes[i], &t) != hipSuccess) return false;
+    uint64_t f = 0;
+    if (t == hipGraphNodeTypeKernel) {
+      hipKernelNodeParams kp{};
+      if (hipGraphKernelNodeGetParams(nodes[i], &kp) != hipSuccess) return false;
+      f = (uint64_t)reinterpret_cast<uintptr_t>(kp.func);
+    }
+    (*topo)[2 * i] = (uint64_t)t;
+    (*topo)[2 * i + 1] = f;
+    for (uint64_t w : {(uint64_t)t, f}) {
+      h ^= w;
+      h *= 1099511628211ull;
+    }
+  }
+  *hash = h;
+  return true;
+}
 
 struct ServeRequest {
   uint64_t ticket;
@@ -109,15 +131,6 @@ struct ServeState {
   int running = 0;
 };
 
-static GraphKey key_of(const ServeRequest &r) {
-  GraphKey k;
-  k.m = r.A.m; k.n = r.A.n; k.nnz = r.A.layout == RLU_CSR ? r.A.nnz : 0;
-  k.layout = r.A.layout; k.dtype = r.A.dtype;
-  k.k = r.p.k; k.l = r.p.l; k.s = r.p.s; k.precision = r.p.precision; k.k2 = r.p.k2; k.l2 = r.p.l2;
-  k.flags = r.p.flags;
-  return k;
-}
-
 // One request's stage sequence on its slot.  On the single exclusive slot:
 // captured into a graph and launched as one (an instantiated graph of the
 // slot updated in place when the topology allows, else a new one, the least
@@ -146,10 +159,16 @@ static rlu_status launch_request(ServeState *s, ServeSlot &sl, const ServeReques
     ++s->graph_fallbacks;
     return factor_enqueue(*s->cx, &r.A, &r.p, &r.out, ws, r.fp, sl.st, &env);
   }
-  const GraphKey key = key_of(r);
+  std::vector<uint64_t> topo;
+  uint64_t hash = 0;
+  if (!graph_topology(g, &topo, &hash)) {
+    (void)hipGetLastError();
+    topo.clear();
+    hash = 0;  // an entry that no later topology matches
+  }
   GraphEntry *hit = nullptr;
   for (GraphEntry &ge : sl.graphs)
-    if (ge.key == key) { hit = &ge; break; }
+    if (!topo.empty() && ge.hash == hash && ge.topo == topo) { hit = &ge; break; }
   hipGraphExec_t exec = nullptr;
   if (hit) {
     hipGraphNode_t err_node = nullptr;
@@ -181,7 +200,7 @@ static rlu_status launch_request(ServeState *s, ServeSlot &sl, const ServeReques
         (void)hipGraphExecDestroy(sl.graphs[lru].exec);
         sl.graphs.erase(sl.graphs.begin() + lru);
       }
-      sl.graphs.push_back(GraphEntry{key, nullptr, 0});
+      sl.graphs.push_back(GraphEntry{hash, std::move(topo), nullptr, 0});
       hit = &sl.graphs.back();
     }
     hit->exec = exec;
