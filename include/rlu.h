@@ -101,7 +101,7 @@ typedef struct {
   const void *values;       /* dense: m x n row major; CSR: nnz values             */
   int64_t ld;               /* dense: leading dimension >= n                       */
   const int32_t *row_ptr;   /* CSR: m + 1 offsets, row_ptr[0] = 0, row_ptr[m] = nnz */
-  const int32_t *col_idx;   /* CSR: nnz column indices in [0, n)                   */
+  const int32_t *col_idx;   /* CSR: nnz column indices in [0, n); CSR n <= 2^29    */
   int64_t nnz;              /* CSR: number of stored entries                       */
 } rlu_matrix;
 

@@ -56,6 +56,7 @@ rlu_status validate_matrix(const rlu_matrix *A) {
     if (!A->row_ptr) return fail(RLU_ERR_INVALID_ARG, "CSR row_ptr is NULL");
     if (!A->col_idx && A->nnz > 0) return fail(RLU_ERR_INVALID_ARG, "CSR col_idx is NULL");
     if (A->nnz < 0 || A->nnz > INT32_MAX) return fail(RLU_ERR_INVALID_ARG, "CSR nnz out of range");
+    if (A->n > ((int64_t)1 << 29)) return fail(RLU_ERR_INVALID_ARG, "CSR n must be at most 2^29");
   } else {
     return fail(RLU_ERR_INVALID_ARG, "unknown layout %d", A->layout);
   }

@@ -178,56 +178,156 @@ hipError_t launch_csr_check(const rlu_matrix *A, int validate_cols, rlu_info *in
 
 // ---- CSC (A^T) build and the sparse contraction -------------------------------------
 
-// CSC copy of A by a two-level counting sort with no device-wide atomics
-// (a device-scope atomic on this chip is performed beyond the per-die L2
-// caches, so one per nonzero into n shared counters is slow).  The nonzeros
-// [0, nnz) are cut into kCscChunks equal chunks and the columns into ranges
-// of kCscRange; block (b, r) owns entry chunk b and column range r, whose
-// counters fit in LDS.  Every entry is enumerated exactly once whatever the
-// row pointers hold, so the positions can never pass nnz.
-//   1. k_csc_hist: LDS counts of the chunk's entries per column, stored as
-//      hist[b][c] (coalesced);
-//   2. k_csc_colscan: per column, the exclusive prefix over the chunks in
-//      place and the column's total; a scan of the totals gives colptr;
-//   3. k_csc_place: the block's LDS cursors start at colptr[c] + hist[b][c]
-//      and the block writes its entries there; each thread takes a contiguous
-//      run of the chunk, finds the row of its first entry by a binary search
-//      of the row pointers and follows the rows along from there.
+// CSC copy of A by a two-pass bucket sort with no device-wide atomics (a
+// device-scope atomic on this chip is performed beyond the per-die L2
+// caches, so one per nonzero into n shared counters is slow), laid out so
+// that the scattered writes of each pass stay within a region that the L2
+// caches can gather into whole lines.  Columns are grouped into Q buckets of
+// R consecutive columns (R = 512, or a larger power of two when n needs it,
+// so that Q <= kMaxBuckets); the nonzeros [0, nnz) are cut into kBktChunks
+// equal chunks.
+//   0. k_csr_rows: the row of every entry (one pass over the row pointers);
+//   1. k_bkt_count: per chunk, LDS counts of its entries per bucket, stored
+//      bucket-major (cnt[q][b]), so that their exclusive scan gives every
+//      (bucket, chunk) pair its run in a bucket-ordered staging array;
+//   2. k_bkt_scatter: each chunk writes its entries (column, row, value) to
+//      its runs, from LDS cursors;
+//   3. k_bkt_place: one block per bucket counts its entries per column in
+//      LDS, scans them into the column pointers and writes every entry to its
+//      column's place, all within the bucket's part of the CSC arrays.
 // A column's entries come chunk by chunk, so in increasing row order across
 // chunks; within one chunk they follow the LDS cursor increments (sorted
-// afterwards in deterministic mode).
-constexpr int kCscRange = 16384;
-constexpr int kCscChunks = 128;
+// afterwards in deterministic mode).  Entries with a column outside [0, n)
+// are left out (the sketch counts them in rlu_info.bad_index).
+constexpr int kBktChunks = 256;
+constexpr int kMaxBuckets = 16384;
+constexpr int kMinBucketCols = 512;
+constexpr int kMaxBucketCols = 32768;
 constexpr int kScanTile = 4096;
+constexpr int kBktUnroll = 8;  // entries per lane per pass, their loads issued together
 
-__global__ __launch_bounds__(256) void k_csc_hist(int64_t n, int64_t nnz, const int32_t *__restrict__ col,
-                                                  int32_t *__restrict__ hist) {
-  __shared__ int32_t h[kCscRange];
-  const int tid = threadIdx.x;
-  const int B = gridDim.x, b = blockIdx.x;
-  const int64_t c0 = (int64_t)blockIdx.y * kCscRange;
-  const int cw = (int)min<int64_t>(kCscRange, n - c0);
-  for (int i = tid; i < cw; i += 256) h[i] = 0;
-  __syncthreads();
-  const int64_t k0 = nnz * b / B, k1 = nnz * (b + 1) / B;
-  for (int64_t k = k0 + tid; k < k1; k += 256) {
-    const int64_t c = (int64_t)col[k] - c0;
-    if (c >= 0 && c < cw) atomicAdd(&h[c], 1);
-  }
-  __syncthreads();
-  for (int i = tid; i < cw; i += 256) hist[(int64_t)b * n + c0 + i] = h[i];
+static int bucket_cols(int64_t n) {
+  int64_t r = kMinBucketCols;
+  while (ceil_div(n, r) > kMaxBuckets) r *= 2;
+  return (int)r;
 }
 
-// per column: exclusive prefix over the chunks in place, the total in tot
-__global__ void k_csc_colscan(int64_t n, int B, int32_t *__restrict__ hist, int32_t *__restrict__ tot) {
-  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
-    int32_t run = 0;
-    for (int b = 0; b < B; ++b) {
-      const int32_t x = hist[(int64_t)b * n + c];
-      hist[(int64_t)b * n + c] = run;
-      run += x;
+__global__ __launch_bounds__(256) void k_bkt_count(int64_t n, int64_t nnz, int R, int Q,
+                                                   const int32_t *__restrict__ col, int32_t *__restrict__ cnt) {
+  extern __shared__ int32_t h[];  // Q counters
+  const int tid = threadIdx.x, B = gridDim.x, b = blockIdx.x;
+  for (int q = tid; q < Q; q += 256) h[q] = 0;
+  __syncthreads();
+  const int64_t k0 = nnz * b / B, k1 = nnz * (b + 1) / B;
+  for (int64_t kb = k0 + tid; kb < k1; kb += 256 * kBktUnroll) {  // kBktUnroll loads in flight per lane
+    int32_t c[kBktUnroll];
+#pragma unroll
+    for (int u = 0; u < kBktUnroll; ++u) c[u] = kb + 256 * u < k1 ? col[kb + 256 * u] : -1;
+#pragma unroll
+    for (int u = 0; u < kBktUnroll; ++u)
+      if (c[u] >= 0 && c[u] < n) atomicAdd(&h[c[u] / R], 1);
+  }
+  __syncthreads();
+  for (int q = tid; q < Q; q += 256) cnt[(int64_t)q * B + b] = h[q];
+}
+
+struct BktEntry {
+  int32_t col, row;
+  double val;
+};
+
+__global__ __launch_bounds__(256) void k_bkt_scatter(int64_t n, int64_t nnz, int R, int Q,
+                                                     const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                     const int32_t *__restrict__ rowidx,
+                                                     const int32_t *__restrict__ off, BktEntry *__restrict__ stage) {
+  extern __shared__ int32_t cur[];  // Q cursors
+  const int tid = threadIdx.x, B = gridDim.x, b = blockIdx.x;
+  for (int q = tid; q < Q; q += 256) cur[q] = off[(int64_t)q * B + b];
+  __syncthreads();
+  const int64_t k0 = nnz * b / B, k1 = nnz * (b + 1) / B;
+  for (int64_t kb = k0 + tid; kb < k1; kb += 256 * kBktUnroll) {
+    BktEntry e[kBktUnroll];
+#pragma unroll
+    for (int u = 0; u < kBktUnroll; ++u) {
+      const int64_t k = kb + 256 * u;
+      const bool in = k < k1;
+      e[u].col = in ? col[k] : -1;
+      e[u].row = in ? rowidx[k] : 0;
+      e[u].val = in ? val[k] : 0.0;
     }
-    tot[c] = run;
+#pragma unroll
+    for (int u = 0; u < kBktUnroll; ++u) {
+      if (e[u].col < 0 || e[u].col >= n) continue;
+      const int32_t pos = atomicAdd(&cur[e[u].col / R], 1);
+      stage[pos] = e[u];
+    }
+  }
+}
+
+// One block (1024 threads) per bucket q: its entries are stage[off[q B] ..
+// off[(q + 1) B]), its columns q R .. q R + R - 1.
+__global__ __launch_bounds__(1024) void k_bkt_place(int64_t n, int R, int Q, int B, const int32_t *__restrict__ off,
+                                                    const BktEntry *__restrict__ stage, int32_t *__restrict__ colptr,
+                                                    int32_t *__restrict__ crow, double *__restrict__ cval) {
+  extern __shared__ int32_t cc[];  // R counters, then cursors
+  __shared__ int32_t wsum[16];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int q = blockIdx.x;
+  const int64_t c0 = (int64_t)q * R;
+  const int cw = (int)min<int64_t>(R, n - c0);
+  const int32_t e0 = off[(int64_t)q * B], e1 = off[(int64_t)(q + 1) * B];
+  for (int i = tid; i < cw; i += 1024) cc[i] = 0;
+  __syncthreads();
+  for (int32_t eb = e0 + tid; eb < e1; eb += 1024 * kBktUnroll) {
+    int32_t c[kBktUnroll];
+#pragma unroll
+    for (int u = 0; u < kBktUnroll; ++u) c[u] = eb + 1024 * u < e1 ? stage[eb + 1024 * u].col - (int32_t)c0 : -1;
+#pragma unroll
+    for (int u = 0; u < kBktUnroll; ++u)
+      if (c[u] >= 0) atomicAdd(&cc[c[u]], 1);
+  }
+  __syncthreads();
+  // exclusive scan of the cw counts, 1024 at a time, from e0
+  int32_t base = e0;
+  for (int i0 = 0; i0 < cw; i0 += 1024) {
+    const int i = i0 + tid;
+    const int32_t x = i < cw ? cc[i] : 0;
+    int32_t incl = x;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t y = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += y;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int32_t before = base, round = 0;
+    for (int w = 0; w < 16; ++w) {
+      before += w < wv ? wsum[w] : 0;
+      round += wsum[w];
+    }
+    if (i < cw) {
+      const int32_t ex = before + incl - x;
+      colptr[c0 + i] = ex;
+      cc[i] = ex;
+    }
+    __syncthreads();
+    base += round;
+  }
+  if (q == Q - 1 && tid == 0) colptr[n] = e1;
+  __syncthreads();
+  for (int32_t eb = e0 + tid; eb < e1; eb += 1024 * kBktUnroll) {
+    BktEntry en[kBktUnroll];
+#pragma unroll
+    for (int u = 0; u < kBktUnroll; ++u) {
+      const int32_t e = eb + 1024 * u < e1 ? eb + 1024 * u : e0;  // past the end: a repeat, not placed
+      en[u] = stage[e];
+    }
+#pragma unroll
+    for (int u = 0; u < kBktUnroll; ++u) {
+      if (eb + 1024 * u >= e1) continue;
+      const int32_t pos = atomicAdd(&cc[en[u].col - (int32_t)c0], 1);
+      crow[pos] = en[u].row;
+      cval[pos] = en[u].val;
+    }
   }
 }
 
@@ -296,40 +396,19 @@ __global__ __launch_bounds__(256) void k_scan_apply(int64_t total, const int32_t
   if (blockIdx.x == gridDim.x - 1 && tid == 0) out[total] = base;
 }
 
-// the row of entry k: the last row i with row_ptr[i] <= k (clamped to [0, m))
-__device__ inline int64_t row_of(int64_t m, const int32_t *__restrict__ row_ptr, int64_t k) {
-  int64_t lo = 0, hi = m - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if ((int64_t)row_ptr[mid] <= k) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-__global__ __launch_bounds__(256) void k_csc_place(int64_t m, int64_t n, int64_t nnz,
-                                                   const int32_t *__restrict__ row_ptr,
-                                                   const int32_t *__restrict__ col, const double *__restrict__ val,
-                                                   const int32_t *__restrict__ colptr, const int32_t *__restrict__ hist,
-                                                   int32_t *__restrict__ crow, double *__restrict__ cval) {
-  __shared__ int32_t cur[kCscRange];
-  const int tid = threadIdx.x;
-  const int B = gridDim.x, b = blockIdx.x;
-  const int64_t c0 = (int64_t)blockIdx.y * kCscRange;
-  const int cw = (int)min<int64_t>(kCscRange, n - c0);
-  for (int i = tid; i < cw; i += 256) cur[i] = colptr[c0 + i] + hist[(int64_t)b * n + c0 + i];
-  __syncthreads();
-  // each thread a contiguous run of the chunk's entries, so that its row is
-  // found once by binary search and then only moves forward
-  const int64_t k0 = nnz * b / B, k1 = nnz * (b + 1) / B, len = k1 - k0;
-  const int64_t ka = k0 + len * tid / 256, kb = k0 + len * (tid + 1) / 256;
-  int64_t row = ka < kb ? row_of(m, row_ptr, ka) : 0;
-  for (int64_t k = ka; k < kb; ++k) {
-    const int64_t c = (int64_t)col[k] - c0;
-    if (c < 0 || c >= cw) continue;
-    while (row + 1 < m && (int64_t)row_ptr[row + 1] <= k) ++row;
-    const int32_t p = atomicAdd(&cur[c], 1);
-    crow[p] = (int32_t)row;
-    cval[p] = val[k];
+// The row of every entry, written row by row (one wavefront per row):
+// rowidx[k] = i for k in [row_ptr[i], row_ptr[i+1]).  Consistent row
+// pointers cover every entry exactly once; with inconsistent ones (flagged
+// by the row pointer check) an entry keeps row 0 or takes one of the rows
+// that claim it, always a valid row.
+__global__ __launch_bounds__(256) void k_csr_rows(int64_t m, int64_t nnz, const int32_t *__restrict__ row_ptr,
+                                                  int32_t *__restrict__ rowidx) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = w0; i < m; i += nw) {
+    const int64_t a = clamp_ptr(row_ptr[i], nnz), b = clamp_ptr(row_ptr[i + 1], nnz);
+    for (int64_t k = a + lane; k < b; k += 64) rowidx[k] = (int32_t)i;
   }
 }
 
@@ -442,23 +521,28 @@ __global__ __launch_bounds__(256) void k_spmm_t(int64_t n, int l, const int32_t 
   }
 }
 
-static int64_t csc_tiles(int64_t n) { return ceil_div(n, kScanTile); }
-
 size_t csc_scratch_bytes(int64_t n, int64_t nnz) {
-  return align_up((size_t)n * kCscChunks * 4, 256) + align_up((size_t)n * 4, 256) +
-         align_up((size_t)csc_tiles(n) * 4, 256) + align_up((size_t)(n + 1) * 4, 256) +
-         align_up((size_t)nnz * 4, 256) + align_up((size_t)nnz * 8, 256);
+  const int64_t Q = ceil_div(std::max<int64_t>(n, 1), bucket_cols(n));
+  const int64_t cells = Q * kBktChunks;
+  return align_up((size_t)cells * 4, 256) + align_up((size_t)(cells + 1) * 4, 256) +
+         align_up((size_t)ceil_div(cells, kScanTile) * 4, 256) +
+         align_up((size_t)(n + 1) * 4, 256) + align_up((size_t)nnz * 4, 256) + align_up((size_t)nnz * 8, 256) +
+         align_up((size_t)nnz * 4, 256) + align_up((size_t)nnz * sizeof(BktEntry), 256);
 }
 
 hipError_t build_csc(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
                      int64_t nnz, void *scratch, int num_cu, bool sorted, hipStream_t st, CscView *out) {
-  char *w = reinterpret_cast<char *>(scratch);
-  const int64_t ntiles = csc_tiles(n);
+  const int R = bucket_cols(n);
+  if (R > kMaxBucketCols) return hipErrorInvalidValue;
+  const int Q = (int)ceil_div(std::max<int64_t>(n, 1), R);
+  const int64_t cells = (int64_t)Q * kBktChunks;
+  const int64_t ntiles = ceil_div(cells, kScanTile);
   if (ntiles > 1024 * 1024) return hipErrorInvalidValue;
-  int32_t *hist = reinterpret_cast<int32_t *>(w);
-  w += align_up((size_t)n * kCscChunks * 4, 256);
-  int32_t *tot = reinterpret_cast<int32_t *>(w);
-  w += align_up((size_t)n * 4, 256);
+  char *w = reinterpret_cast<char *>(scratch);
+  int32_t *cnt = reinterpret_cast<int32_t *>(w);  // entries per (bucket, chunk), bucket-major
+  w += align_up((size_t)cells * 4, 256);
+  int32_t *off = reinterpret_cast<int32_t *>(w);  // their exclusive scan, off[cells] = the total
+  w += align_up((size_t)(cells + 1) * 4, 256);
   int32_t *tsum = reinterpret_cast<int32_t *>(w);
   w += align_up((size_t)ntiles * 4, 256);
   int32_t *colptr = reinterpret_cast<int32_t *>(w);
@@ -466,15 +550,33 @@ hipError_t build_csc(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t
   int32_t *crow = reinterpret_cast<int32_t *>(w);
   w += align_up((size_t)nnz * 4, 256);
   double *cval = reinterpret_cast<double *>(w);
-  const dim3 grid(kCscChunks, (unsigned)ceil_div(n, kCscRange));
-  hipLaunchKernelGGL(k_csc_hist, grid, dim3(256), 0, st, n, nnz, col, hist);
-  const int cblocks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, ceil_div(n, 256)));
-  hipLaunchKernelGGL(k_csc_colscan, dim3(cblocks), dim3(256), 0, st, n, kCscChunks, hist, tot);
-  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(256), 0, st, n, tot, tsum);
+  w += align_up((size_t)nnz * 8, 256);
+  int32_t *rowidx = reinterpret_cast<int32_t *>(w);
+  w += align_up((size_t)nnz * 4, 256);
+  BktEntry *stage = reinterpret_cast<BktEntry *>(w);
+  hipError_t e;
+  if (nnz > 0) {
+    if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(rowidx), 0u, nnz, st)) != hipSuccess) return e;
+    const unsigned rb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((int64_t)num_cu * 16, ceil_div(m, 4)));
+    hipLaunchKernelGGL(k_csr_rows, dim3(rb), dim3(256), 0, st, m, nnz, row_ptr, rowidx);
+  }
+  const size_t qlds = (size_t)Q * 4;
+  if ((e = hipFuncSetAttribute((const void *)k_bkt_count, hipFuncAttributeMaxDynamicSharedMemorySize, (int)qlds)) !=
+          hipSuccess ||
+      (e = hipFuncSetAttribute((const void *)k_bkt_scatter, hipFuncAttributeMaxDynamicSharedMemorySize, (int)qlds)) !=
+          hipSuccess ||
+      (e = hipFuncSetAttribute((const void *)k_bkt_place, hipFuncAttributeMaxDynamicSharedMemorySize, R * 4)) !=
+          hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_bkt_count, dim3(kBktChunks), dim3(256), qlds, st, n, nnz, R, Q, col, cnt);
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)ntiles), dim3(256), 0, st, cells, cnt, tsum);
   hipLaunchKernelGGL(k_scan_tile_sums, dim3(1), dim3(1024), 0, st, (int)ntiles, tsum);
-  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(256), 0, st, n, tot, tsum, colptr);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(256), 0, st, cells, cnt, tsum, off);
   if (nnz > 0)
-    hipLaunchKernelGGL(k_csc_place, grid, dim3(256), 0, st, m, n, nnz, row_ptr, col, val, colptr, hist, crow, cval);
+    hipLaunchKernelGGL(k_bkt_scatter, dim3(kBktChunks), dim3(256), qlds, st, n, nnz, R, Q, col, val, rowidx, off,
+                       stage);
+  hipLaunchKernelGGL(k_bkt_place, dim3(Q), dim3(1024), (size_t)R * 4, st, n, R, Q, (int)kBktChunks, off, stage, colptr,
+                     crow, cval);
   if (sorted) {
     const int sblocks = (int)std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)num_cu * 8));
     hipLaunchKernelGGL(k_csc_sort, dim3(sblocks), dim3(256), 0, st, n, colptr, crow, cval);
