@@ -95,7 +95,9 @@ typedef enum {
 } rlu_precision;
 
 typedef struct {
-  int64_t m, n;             /* rows, columns (>= 1)                                */
+  int64_t m, n;             /* rows, columns (>= 1); at most 524288 each for
+                             * rlu_factor: each LU holds its rows in registers
+                             * (256 blocks x 256 threads x 8 rows)              */
   int32_t layout;           /* rlu_layout                                          */
   int32_t dtype;            /* rlu_dtype (CSR: RLU_F64 only)                       */
   const void *values;       /* dense: m x n row major; CSR: nnz values             */

@@ -30,6 +30,8 @@
 // BF16 MFMA operand layouts (v_mfma_f32_16x16x32_bf16): lane l supplies
 // A[l%16][8(l/16) .. 8(l/16)+7] and B[8(l/16) .. 8(l/16)+7][l%16]; element v
 // of the result in lane l is D[4(l/16) + v][l%16].
+#include <type_traits>
+
 #include "rlu_device.h"
 #include "rlu_internal.h"
 
@@ -288,59 +290,103 @@ __global__ __launch_bounds__(256) void k_bf16_tn(Bf16Tn p) {
 // row tile.  K is split into `splits` ranges laid out so that each XCD works
 // on one range, whose slice of Lb^T then stays in that XCD's L2.  Eight waves
 // in a 2 x 4 grid, wave tile 64 x (16 WN), block tile 128 x (64 WN); K
-// advances 32 per stage through a double-buffered LDS tile, the next stage's
-// loads in flight during the current stage's MFMAs (v_mfma_f32_16x16x32_bf16).
-// FP32 partial sums per K range go to `parts` (summed in FP64 afterwards, in
-// a fixed order) or, with one range, straight to C.
+// advances 32 per stage (v_mfma_f32_16x16x32_bf16).  FP32 partial sums per
+// K range go to `parts` (summed in FP64 afterwards, in a fixed order) or,
+// with one range, straight to C.
+//
+// Loads run two stages ahead.  Every 16-byte K-contiguous
+// operand (Lb^T, and X^T when given transposed) goes from global memory
+// straight to LDS (global_load_lds_dwordx4: lane i's 16 bytes land at the
+// wavefront's LDS base + 16 i) into a ring of three stages, issued two
+// stages ahead, so two stages of loads are in flight while a third is
+// multiplied; FP32 / FP64 X goes through registers, two stages ahead in two
+// register sets, and is rounded and transposed into a double-buffered LDS
+// tile.  The ring rows are 64 bytes (32 k) with the four 16-byte chunks of
+// row r permuted by chunk ^ ((r >> 1) & 3), so that the fragment reads of
+// 16 consecutive rows spread over the banks.
 // ---------------------------------------------------------------------------
-template <typename TX, bool XT, int WN>
-__global__ __launch_bounds__(512) void k_bf16_tn_wide(Bf16Tn p) {
-  constexpr int BM = 128, BN = 64 * WN, BK = 32, LS = BK + 8;  // 80-byte rows
-  constexpr int QL = (BN * BK / 8 + 511) / 512;                 // 16-byte chunks of Lb^T per thread
-  __shared__ __attribute__((aligned(16))) uint16_t Xs[2][BM * LS];
-  __shared__ __attribute__((aligned(16))) uint16_t Ls[2][BN * LS];
-  const int64_t t = xcd_tile(p.per_xcd);
-  if (t >= p.tiles) return;
-  const int tm = (int)(t % p.ntm);
-  const int z = (int)(t / p.ntm);  // K range: consecutive tiles (one XCD) share it
-  const int64_t m0 = (int64_t)tm * BM;
-  const int64_t kb = (int64_t)z * p.Kc, ke = min(p.K, kb + p.Kc);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
-  const int xc = tid & 127, xk = tid >> 7;  // transposing loader: column xc, k rows 8 xk .. 8 xk + 7
+__device__ inline int ring_sw(int r) { return (r >> 1) & 3; }
 
-  TX rx[XT ? 1 : 8];
-  u32x4 rxq;
-  u32x4 rlq[QL];
-  auto load = [&](int64_t k0) {
-    if constexpr (XT) {
-      const uint16_t *Xb = reinterpret_cast<const uint16_t *>(p.X);
-      const int r = tid >> 2, kc = tid & 3;
-      const int64_t row = m0 + r < p.M ? m0 + r : m0;
-      rxq = *reinterpret_cast<const u32x4 *>(Xb + row * p.ldx + k0 + kc * 8);
-    } else {
+__device__ inline void lds_direct16(const void *g, uint16_t *lds) {
+  __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
+}
+
+template <typename TX, bool XT, int WN>
+__global__ __launch_bounds__(512) void k_bf16_tn_pipe(Bf16Tn p) {
+  constexpr int BM = 128, BN = 64 * WN, BK = 32, LS = BK + 8;
+  constexpr int NPL = 128 * ((WN + 1) / 2);  // rows of Lb^T per stage (Lb^T is padded to 128 rows)
+  constexpr int LIW = NPL / 16 / 8;          // its direct loads per wavefront per stage
+  constexpr int XIW = XT ? 1 : 8;            // X loads per wavefront (XT) or per lane (FP32 / FP64) per stage
+  // The ring's three stages are three LDS arrays, addressed statically (the
+  // stage loop is unrolled by six), so that the compiler can tell a fragment
+  // read of one stage from the loads in flight into another and does not
+  // wait for those.
+  __shared__ __attribute__((aligned(16))) uint16_t Ls0[NPL * 32], Ls1[NPL * 32], Ls2[NPL * 32];
+  __shared__ __attribute__((aligned(16))) uint16_t Xr0[XT ? BM * 32 : 8], Xr1[XT ? BM * 32 : 8], Xr2[XT ? BM * 32 : 8];
+  __shared__ __attribute__((aligned(16))) uint16_t Xd0[XT ? 8 : BM * LS], Xd1[XT ? 8 : BM * LS];
+  // Tiles by XCD (tile t on XCD t / per_xcd); the grid may hold fewer blocks
+  // than tiles (a multiple of 8), each block then taking every (grid / 8)-th
+  // tile of its XCD's range in turn.
+  const int64_t per_blk = gridDim.x >> 3;
+  for (int64_t tt = blockIdx.x >> 3; tt < p.per_xcd; tt += per_blk) {
+    const int64_t t = (int64_t)(blockIdx.x & 7) * p.per_xcd + tt;
+    if (t >= p.tiles) break;
+    const int tm = (int)(t % p.ntm);
+    const int z = (int)(t / p.ntm);  // K range: consecutive tiles (one XCD) share it
+    const int64_t m0 = (int64_t)tm * BM;
+    const int64_t kb = (int64_t)z * p.Kc, ke = min(p.K, kb + p.Kc);
+    const int nst = (int)ceil_div(ke - kb, BK);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int xc = tid & 127, xk = tid >> 7;  // FP32 / FP64 loader: column xc, k rows 8 xk .. 8 xk + 7
+    const int q = lane >> 4;
+
+    auto lring = [&](auto c) -> uint16_t * {
+      constexpr int C = decltype(c)::value;
+      if constexpr (C == 0) return Ls0;
+      else if constexpr (C == 1) return Ls1;
+      else return Ls2;
+    };
+    auto xring = [&](auto c) -> uint16_t * {
+      constexpr int C = decltype(c)::value;
+      if constexpr (C == 0) return Xr0;
+      else if constexpr (C == 1) return Xr1;
+      else return Xr2;
+    };
+    auto xdbl = [&](auto c) -> uint16_t * {
+      if constexpr (decltype(c)::value == 0) return Xd0;
+      else return Xd1;
+    };
+
+    auto issue = [&](auto slot, int s) {  // direct loads of stage s into ring slot `slot`
+      const int64_t k0 = kb + (int64_t)s * BK;
+      uint16_t *ls = lring(slot);
+#pragma unroll
+      for (int i = 0; i < LIW; ++i) {
+        const int r0 = (wave * LIW + i) * 16;
+        const int r = r0 + (lane >> 2), kc = (lane & 3) ^ ring_sw(r);
+        lds_direct16(p.LbT + (int64_t)r * p.ldl + k0 + kc * 8, ls + r0 * 32);
+      }
+      if constexpr (XT) {
+        const uint16_t *Xb = reinterpret_cast<const uint16_t *>(p.X);
+        const int r0 = wave * 16;
+        const int r = r0 + (lane >> 2), kc = (lane & 3) ^ ring_sw(r);
+        const int64_t row = m0 + r < p.M ? m0 + r : m0;  // rows past M: a copy of row m0, never stored
+        lds_direct16(Xb + row * p.ldx + k0 + kc * 8, xring(slot) + r0 * 32);
+      }
+    };
+    auto load_x = [&](TX (&rx)[8], int s) {  // FP32 / FP64 X of stage s into registers
       const TX *X = reinterpret_cast<const TX *>(p.X);
-      const int64_t col = m0 + xc;
+      const int64_t k0 = kb + (int64_t)s * BK, col = m0 + xc;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int64_t k = k0 + xk * 8 + e;
         const bool ok = k < ke && col < p.M;
         rx[e] = X[(ok ? k : kb) * p.ldx + (ok ? col : m0)];
       }
-    }
-#pragma unroll
-    for (int q = 0; q < QL; ++q) {
-      const int e = tid + 512 * q;
-      const int r = min(e >> 2, p.ntn - 1), kc = e & 3;  // ntn: rows of Lb^T available
-      rlq[q] = *reinterpret_cast<const u32x4 *>(p.LbT + (int64_t)r * p.ldl + k0 + kc * 8);
-    }
-  };
-  auto store = [&](int buf, int64_t k0) {
-    const u32x4 zero = {0u, 0u, 0u, 0u};
-    if constexpr (XT) {
-      const int r = tid >> 2, kc = tid & 3;
-      *reinterpret_cast<u32x4 *>(&Xs[buf][r * LS + kc * 8]) = m0 + r < p.M ? rxq : zero;
-    } else {
+    };
+    auto store_x = [&](const TX (&rx)[8], auto par, int s) {  // ... rounded and transposed into an Xd tile
+      const int64_t k0 = kb + (int64_t)s * BK;
       const bool cok = m0 + xc < p.M;
       TX v[8];
 #pragma unroll
@@ -350,65 +396,98 @@ __global__ __launch_bounds__(512) void k_bf16_tn_wide(Bf16Tn p) {
       w.y = pack_bf16(v[2], v[3]);
       w.z = pack_bf16(v[4], v[5]);
       w.w = pack_bf16(v[6], v[7]);
-      *reinterpret_cast<u32x4 *>(&Xs[buf][xc * LS + xk * 8]) = w;
-    }
+      *reinterpret_cast<u32x4 *>(xdbl(par) + xc * LS + xk * 8) = w;
+    };
+
+    f32x4 acc[4][WN];
 #pragma unroll
-    for (int q = 0; q < QL; ++q) {
-      const int e = tid + 512 * q;
-      if (e < BN * BK / 8) {
-        const int r = e >> 2, kc = e & 3;
-        *reinterpret_cast<u32x4 *>(&Ls[buf][r * LS + kc * 8]) = r < p.ntn ? rlq[q] : zero;
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    auto mfma_stage = [&](auto slot, auto par) {
+      bf16x8 a[4], b[WN];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = wm * 64 + i * 16 + (lane & 15);
+        if constexpr (XT) a[i] = *reinterpret_cast<const bf16x8 *>(xring(slot) + r * 32 + ((q ^ ring_sw(r)) * 8));
+        else a[i] = *reinterpret_cast<const bf16x8 *>(xdbl(par) + r * LS + q * 8);
       }
-    }
-  };
+      const uint16_t *ls = lring(slot);
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const int r = wn * 16 * WN + j * 16 + (lane & 15);
+        b[j] = *reinterpret_cast<const bf16x8 *>(ls + r * 32 + ((q ^ ring_sw(r)) * 8));
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    };
 
-  f32x4 acc[4][WN];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  int buf = 0;
-  if (kb < ke) {
-    load(kb);
-    store(0, kb);
-    __syncthreads();
-  }
-  const int ko = 8 * (lane >> 4);
-  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
-    const bool more = k0 + BK < ke;
-    if (more) load(k0 + BK);
-    bf16x8 a[4], b[WN];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      a[i] = *reinterpret_cast<const bf16x8 *>(&Xs[buf][(wm * 64 + i * 16 + (lane & 15)) * LS + ko]);
-#pragma unroll
-    for (int j = 0; j < WN; ++j)
-      b[j] = *reinterpret_cast<const bf16x8 *>(&Ls[buf][(wn * 16 * WN + j * 16 + (lane & 15)) * LS + ko]);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < WN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    if (more) {
-      store(buf ^ 1, k0 + BK);
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    TX rx0[8], rx1[8];
+    if (nst > 0) {
+      issue(I0{}, 0);
+      if constexpr (!XT) load_x(rx0, 0);
+      if (nst > 1) {
+        issue(I1{}, 1);
+        if constexpr (!XT) load_x(rx1, 1);
+      }
+      if constexpr (!XT) store_x(rx0, I0{}, 0);
+      if (nst > 1) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LIW + XIW) : "memory");
+      else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
-      buf ^= 1;
     }
-  }
+    // Stage s (ring slot s % 3, X parity s % 2): loads of stage s + 2 out,
+    // MFMAs of stage s, stage s + 1 made ready (its X rounded into LDS; its
+    // loads waited for, the two stages just issued left in flight).
+    auto step = [&](auto slot, auto par, int s) {
+      constexpr int SL = decltype(slot)::value, PAR = decltype(par)::value;
+      using Next = std::integral_constant<int, (SL + 1) % 3>;
+      using Ahead = std::integral_constant<int, (SL + 2) % 3>;
+      using NPar = std::integral_constant<int, 1 - PAR>;
+      TX(&rfree)[8] = PAR == 0 ? rx0 : rx1;
+      TX(&rnext)[8] = PAR == 0 ? rx1 : rx0;
+      const bool ahead = s + 2 < nst;
+      if (ahead) {
+        issue(Ahead{}, s + 2);
+        if constexpr (!XT) load_x(rfree, s + 2);
+      }
+      mfma_stage(slot, par);
+      if (s + 1 < nst) {
+        if constexpr (!XT) store_x(rnext, NPar{}, s + 1);
+        if (ahead) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LIW + XIW) : "memory");
+        else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+      }
+      (void)sizeof(Next);
+    };
+    for (int s = 0; s < nst; s += 6) {
+      step(I0{}, I0{}, s);
+      if (s + 1 < nst) step(I1{}, I1{}, s + 1);
+      if (s + 2 < nst) step(I2{}, I0{}, s + 2);
+      if (s + 3 < nst) step(I0{}, I1{}, s + 3);
+      if (s + 4 < nst) step(I1{}, I0{}, s + 4);
+      if (s + 5 < nst) step(I2{}, I1{}, s + 5);
+    }
 
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < WN; ++j)
+      for (int j = 0; j < WN; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + v;
-        const int64_t col = wn * 16 * WN + j * 16 + (lane & 15);
-        if (row < p.M && col < p.N) {
-          if (p.parts) p.parts[(int64_t)z * p.M * p.N + row * p.N + col] = acc[i][j][v];
-          else p.C[row * p.ldc + col] = (double)acc[i][j][v];
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + v;
+          const int64_t col = wn * 16 * WN + j * 16 + (lane & 15);
+          if (row < p.M && col < p.N) {
+            if (p.parts) p.parts[(int64_t)z * p.M * p.N + row * p.N + col] = acc[i][j][v];
+            else p.C[row * p.ldc + col] = (double)acc[i][j][v];
+          }
         }
-      }
+    __syncthreads();  // the next tile's first loads go into the ring slots just read
+  }
 }
 
 __global__ void k_sum_parts(int64_t M, int64_t N, int splits, const float *__restrict__ parts, double *__restrict__ C,
@@ -650,10 +729,11 @@ static unsigned ew_blocks(int64_t total) { return (unsigned)std::max<int64_t>(1,
 
 template <typename TX, bool XT>
 static hipError_t launch_tn_wide(const Bf16Tn &k, int wn, unsigned grid, hipStream_t st) {
+  if (k.ntn < 128 * ((wn + 1) / 2)) return hipErrorInvalidValue;  // rows of Lb^T the ring loads
   switch (wn) {
 #define RLU_WIDE(W)                                                                          \
   case W:                                                                                    \
-    hipLaunchKernelGGL((k_bf16_tn_wide<TX, XT, W>), dim3(grid), dim3(512), 0, st, k);         \
+    hipLaunchKernelGGL((k_bf16_tn_pipe<TX, XT, W>), dim3(grid), dim3(512), 0, st, k);         \
     break;
     RLU_WIDE(3) RLU_WIDE(4) RLU_WIDE(5) RLU_WIDE(6) RLU_WIDE(7) RLU_WIDE(8) RLU_WIDE(9)
 #undef RLU_WIDE
