@@ -385,14 +385,14 @@ def sweep_params(r, n):
     return dict(k=r, l=l, s=min(s, 8192))
 
 
-def accuracy_block(rlu, ctx, dev, n=5000, ranks_41=(50, 100, 200, 300, 400, 500),
-                   ranks_42=(10, 50, 100, 200, 300, 400, 500), steps=3):
+def accuracy_block(rlu, ctx, dev, n=5000, ranks_41=(50, 100, 200, 300, 400, 500, 600, 700, 800, 900),
+                   ranks_42=(10, 50, 100, 200, 300, 400, 500, 600, 700, 800, 900), steps=3):
     """The accuracy experiments of Section 4.1 and 4.2 on n x n matrices
     (singular vectors random): the error ||LU - PAQ||_F against
     Delta_r = sqrt(sum_{i > r} sigma_i^2) and the time per decomposition.
     4.1: sigma_1..r = 1, the rest from e^-10 down to e^-200, r varying (the
     matrix changes with r); 4.2: sigma from 1 down to e^-100, one matrix,
-    rank r varying.  Ranks stop at 500 (l <= 544 in this library)."""
+    rank r varying.  Ranks up to 900, the largest of Section 4.1 (l = r + 10)."""
     import numpy as np
     import torch
     import synth

@@ -21,7 +21,7 @@ def test_extras_list_names_every_block():
     assert set(bench.EXTRAS) == {"transforms", "second_projection", "forms", "csr", "serving", "accuracy"}
 
 
-@pytest.mark.parametrize("r,l,s", [(10, 20, 128), (50, 60, 256), (200, 210, 1024), (500, 510, 2048)])
+@pytest.mark.parametrize("r,l,s", [(10, 20, 128), (50, 60, 256), (200, 210, 1024), (500, 510, 2048), (900, 910, 4096)])
 def test_sweep_parameters(r, l, s):
     # k = r, l = r + 10, s the power of two at or above 4 l
     assert bench.sweep_params(r, 5000) == dict(k=r, l=l, s=s)
