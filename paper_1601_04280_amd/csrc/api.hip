@@ -183,7 +183,7 @@ rlu_status plan_factor(const DevCaps &caps, const rlu_matrix *A, const rlu_param
   fp->Up = cv.take((size_t)l * l * 8);
   fp->Lt = cv.take((size_t)l * l * 8);
   fp->gaps = cv.take((size_t)2 * l * 8);
-  fp->csc = cv.take(A->layout == RLU_CSR ? csc_scratch_bytes(n, A->nnz) : 0);
+  fp->csc = cv.take(A->layout == RLU_CSR ? csc_scratch_bytes(n, A->nnz, m, l) : 0);
   fp->pp = PrecPlan{};
   if (A->layout == RLU_DENSE_ROW_MAJOR && p->precision != RLU_PREC_F64 &&
       !plan_precision(m, n, l, p->precision, caps.num_cu, &fp->pp))

@@ -78,7 +78,9 @@ hipError_t launch_sketch_csr(int64_t m, int64_t n, const int32_t *row_ptr, const
                              const int32_t *sel, const double2 *twp, const double *gctab, double *Y,
                              int64_t ldy, int32_t *bad_index, int num_cu, bool hadamard, hipStream_t st);
 hipError_t launch_csr_check(const rlu_matrix *A, int validate_rows, rlu_info *info, hipStream_t st);
-size_t csc_scratch_bytes(int64_t n, int64_t nnz);
+// (with m and l: also room for the contraction's copy of Lhat with rows
+// padded to whole 128-byte lines)
+size_t csc_scratch_bytes(int64_t n, int64_t nnz, int64_t m = 0, int l = 0);
 // CSC copy of CSR A in `scratch` (csc_scratch_bytes): column pointers (n + 1),
 // row indices and values; entries of a column in no particular order, or by
 // ascending row when `sorted`

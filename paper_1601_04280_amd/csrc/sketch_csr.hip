@@ -466,14 +466,15 @@ __global__ __launch_bounds__(256) void k_csc_sort(int64_t n, const int32_t *__re
   }
 }
 
-// W^T[j][:] = sum over column j of A: v * Lhat[row][:]   (one wavefront per column)
+// W^T[j][:] = sum over column j of A: v * Lhat[row][:]   (one wavefront per column;
+// Lhat's rows ldh apart)
 // The column's entries are taken UNR at a time: the UNR rows of Lhat are all
 // loaded before any is used (UNR x QPL loads in flight per lane), then added
 // in entry order, so the sums are the same as one entry at a time.
 template <int QPL>
 __global__ __launch_bounds__(256) void k_spmm_t(int64_t n, int l, const int32_t *__restrict__ colptr,
                                                 const int32_t *__restrict__ crow, const double *__restrict__ cval,
-                                                const double *__restrict__ Lhat, double *__restrict__ Wt) {
+                                                const double *__restrict__ Lhat, int64_t ldh, double *__restrict__ Wt) {
   constexpr int UNR = QPL <= 2 ? 8 : (QPL <= 4 ? 4 : 2);
   const int lane = threadIdx.x & 63;
   const int64_t waves = (int64_t)gridDim.x * 4;
@@ -497,7 +498,7 @@ __global__ __launch_bounds__(256) void k_spmm_t(int64_t n, int l, const int32_t 
           const int lo32 = __builtin_amdgcn_readlane((int)(uint32_t)bits, eu);
           const int hi32 = __builtin_amdgcn_readlane((int)(uint32_t)(bits >> 32), eu);
           ve[u] = e0 + u < cnt ? __longlong_as_double(((int64_t)(uint32_t)hi32 << 32) | (uint32_t)lo32) : 0.0;
-          const double *lr = Lhat + (int64_t)re * l;
+          const double *lr = Lhat + (int64_t)re * ldh;
 #pragma unroll
           for (int t = 0; t < QPL; ++t) {
             const int q = lane + 64 * t;
@@ -521,13 +522,17 @@ __global__ __launch_bounds__(256) void k_spmm_t(int64_t n, int l, const int32_t 
   }
 }
 
-size_t csc_scratch_bytes(int64_t n, int64_t nnz) {
+static int padded_ld(int l) { return (int)ceil_div(l, 16) * 16; }  // 16 doubles: one 128-byte line
+
+size_t csc_scratch_bytes(int64_t n, int64_t nnz, int64_t m, int l) {
   const int64_t Q = ceil_div(std::max<int64_t>(n, 1), bucket_cols(n));
   const int64_t cells = Q * kBktChunks;
-  return align_up((size_t)cells * 4, 256) + align_up((size_t)(cells + 1) * 4, 256) +
-         align_up((size_t)ceil_div(cells, kScanTile) * 4, 256) +
-         align_up((size_t)(n + 1) * 4, 256) + align_up((size_t)nnz * 4, 256) + align_up((size_t)nnz * 8, 256) +
-         align_up((size_t)nnz * 4, 256) + align_up((size_t)nnz * sizeof(BktEntry), 256);
+  size_t b = align_up((size_t)cells * 4, 256) + align_up((size_t)(cells + 1) * 4, 256) +
+             align_up((size_t)ceil_div(cells, kScanTile) * 4, 256) +
+             align_up((size_t)(n + 1) * 4, 256) + align_up((size_t)nnz * 4, 256) + align_up((size_t)nnz * 8, 256) +
+             align_up((size_t)nnz * 4, 256) + align_up((size_t)nnz * sizeof(BktEntry), 256);
+  if (l > 0 && padded_ld(l) != l) b += align_up((size_t)m * padded_ld(l) * 8, 256);
+  return b;
 }
 
 hipError_t build_csc(int64_t m, int64_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
@@ -595,11 +600,23 @@ hipError_t contraction_csr(int64_t m, int64_t n, int l, const int32_t *row_ptr, 
   if (e != hipSuccess) return e;
   const int32_t *colptr = cs.colptr, *crow = cs.crow;
   const double *cval = cs.cval;
+  // The gathers read one row of Lhat per nonzero: with rows padded to whole
+  // 128-byte lines (and line-aligned) each row takes ceil(l / 16) lines
+  // instead of one more for most rows, so Lhat is copied first when l is not
+  // a multiple of 16 (its copy moves 2 m l 8 bytes; the gathers nnz l 8).
+  const double *Lg = Lhat;
+  int64_t ldg = l;
+  if (padded_ld(l) != l) {
+    double *Lp = reinterpret_cast<double *>(reinterpret_cast<char *>(scratch) + csc_scratch_bytes(n, nnz));
+    if ((e = launch_copy_rows(m, l, Lhat, l, Lp, padded_ld(l), st)) != hipSuccess) return e;
+    Lg = Lp;
+    ldg = padded_ld(l);
+  }
   const int qpl = csr_qpl(l);
   const int cblocks = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 4), (int64_t)num_cu * 16));
 #define RLU_SPMM_Q(Q)                                                                                  \
   case Q:                                                                                              \
-    hipLaunchKernelGGL(k_spmm_t<Q>, dim3(cblocks), dim3(256), 0, st, n, l, colptr, crow, cval, Lhat, Wt); \
+    hipLaunchKernelGGL(k_spmm_t<Q>, dim3(cblocks), dim3(256), 0, st, n, l, colptr, crow, cval, Lg, ldg, Wt); \
     break;
   switch (qpl) {
     RLU_SPMM_Q(1) RLU_SPMM_Q(2) RLU_SPMM_Q(3) RLU_SPMM_Q(4) RLU_SPMM_Q(5) RLU_SPMM_Q(6) RLU_SPMM_Q(7)
