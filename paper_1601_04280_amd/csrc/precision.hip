@@ -316,7 +316,6 @@ __global__ __launch_bounds__(512) void k_bf16_tn_pipe(Bf16Tn p) {
   constexpr int BM = 128, BN = 64 * WN, BK = 32, LS = BK + 8;
   constexpr int NPL = 128 * ((WN + 1) / 2);  // rows of Lb^T per stage (Lb^T is padded to 128 rows)
   constexpr int LIW = NPL / 16 / 8;          // its direct loads per wavefront per stage
-  constexpr int XIW = XT ? 1 : 8;            // X loads per wavefront (XT) or per lane (FP32 / FP64) per stage
   // The ring's three stages are three LDS arrays, addressed statically (the
   // stage loop is unrolled by six), so that the compiler can tell a fragment
   // read of one stage from the loads in flight into another and does not
@@ -324,170 +323,170 @@ __global__ __launch_bounds__(512) void k_bf16_tn_pipe(Bf16Tn p) {
   __shared__ __attribute__((aligned(16))) uint16_t Ls0[NPL * 32], Ls1[NPL * 32], Ls2[NPL * 32];
   __shared__ __attribute__((aligned(16))) uint16_t Xr0[XT ? BM * 32 : 8], Xr1[XT ? BM * 32 : 8], Xr2[XT ? BM * 32 : 8];
   __shared__ __attribute__((aligned(16))) uint16_t Xd0[XT ? 8 : BM * LS], Xd1[XT ? 8 : BM * LS];
-  // Tiles by XCD (tile t on XCD t / per_xcd); the grid may hold fewer blocks
-  // than tiles (a multiple of 8), each block then taking every (grid / 8)-th
-  // tile of its XCD's range in turn.
-  const int64_t per_blk = gridDim.x >> 3;
-  for (int64_t tt = blockIdx.x >> 3; tt < p.per_xcd; tt += per_blk) {
-    const int64_t t = (int64_t)(blockIdx.x & 7) * p.per_xcd + tt;
-    if (t >= p.tiles) break;
-    const int tm = (int)(t % p.ntm);
-    const int z = (int)(t / p.ntm);  // K range: consecutive tiles (one XCD) share it
-    const int64_t m0 = (int64_t)tm * BM;
-    const int64_t kb = (int64_t)z * p.Kc, ke = min(p.K, kb + p.Kc);
-    const int nst = (int)ceil_div(ke - kb, BK);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
-    const int xc = tid & 127, xk = tid >> 7;  // FP32 / FP64 loader: column xc, k rows 8 xk .. 8 xk + 7
-    const int q = lane >> 4;
+  const int64_t t = xcd_tile(p.per_xcd);
+  if (t >= p.tiles) return;
+  const int tm = (int)(t % p.ntm);
+  const int z = (int)(t / p.ntm);  // K range: consecutive tiles (one XCD) share it
+  const int64_t m0 = (int64_t)tm * BM;
+  const int64_t kb = (int64_t)z * p.Kc, ke = min(p.K, kb + p.Kc);
+  const int nst = (int)ceil_div(ke - kb, BK);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int xc = tid & 127, xk = tid >> 7;  // FP32 / FP64 loader: column xc, k rows 8 xk .. 8 xk + 7
+  const int q = lane >> 4;
 
-    auto lring = [&](auto c) -> uint16_t * {
-      constexpr int C = decltype(c)::value;
-      if constexpr (C == 0) return Ls0;
-      else if constexpr (C == 1) return Ls1;
-      else return Ls2;
-    };
-    auto xring = [&](auto c) -> uint16_t * {
-      constexpr int C = decltype(c)::value;
-      if constexpr (C == 0) return Xr0;
-      else if constexpr (C == 1) return Xr1;
-      else return Xr2;
-    };
-    auto xdbl = [&](auto c) -> uint16_t * {
-      if constexpr (decltype(c)::value == 0) return Xd0;
-      else return Xd1;
-    };
+  auto lring = [&](auto c) -> uint16_t * {
+    constexpr int C = decltype(c)::value;
+    if constexpr (C == 0) return Ls0;
+    else if constexpr (C == 1) return Ls1;
+    else return Ls2;
+  };
+  auto xring = [&](auto c) -> uint16_t * {
+    constexpr int C = decltype(c)::value;
+    if constexpr (C == 0) return Xr0;
+    else if constexpr (C == 1) return Xr1;
+    else return Xr2;
+  };
+  auto xdbl = [&](auto c) -> uint16_t * {
+    if constexpr (decltype(c)::value == 0) return Xd0;
+    else return Xd1;
+  };
 
-    auto issue = [&](auto slot, int s) {  // direct loads of stage s into ring slot `slot`
-      const int64_t k0 = kb + (int64_t)s * BK;
-      uint16_t *ls = lring(slot);
+  auto issue = [&](auto slot, int s) {  // direct loads of stage s into ring slot `slot`
+    const int64_t k0 = kb + (int64_t)s * BK;
+    uint16_t *ls = lring(slot);
 #pragma unroll
-      for (int i = 0; i < LIW; ++i) {
-        const int r0 = (wave * LIW + i) * 16;
-        const int r = r0 + (lane >> 2), kc = (lane & 3) ^ ring_sw(r);
-        lds_direct16(p.LbT + (int64_t)r * p.ldl + k0 + kc * 8, ls + r0 * 32);
-      }
-      if constexpr (XT) {
-        const uint16_t *Xb = reinterpret_cast<const uint16_t *>(p.X);
-        const int r0 = wave * 16;
-        const int r = r0 + (lane >> 2), kc = (lane & 3) ^ ring_sw(r);
-        const int64_t row = m0 + r < p.M ? m0 + r : m0;  // rows past M: a copy of row m0, never stored
-        lds_direct16(Xb + row * p.ldx + k0 + kc * 8, xring(slot) + r0 * 32);
-      }
-    };
-    auto load_x = [&](TX (&rx)[8], int s) {  // FP32 / FP64 X of stage s into registers
-      const TX *X = reinterpret_cast<const TX *>(p.X);
-      const int64_t k0 = kb + (int64_t)s * BK, col = m0 + xc;
+    for (int i = 0; i < LIW; ++i) {
+      const int r0 = (wave * LIW + i) * 16;
+      const int r = r0 + (lane >> 2), kc = (lane & 3) ^ ring_sw(r);
+      lds_direct16(p.LbT + (int64_t)r * p.ldl + k0 + kc * 8, ls + r0 * 32);
+    }
+    if constexpr (XT) {
+      const uint16_t *Xb = reinterpret_cast<const uint16_t *>(p.X);
+      const int r0 = wave * 16;
+      const int r = r0 + (lane >> 2), kc = (lane & 3) ^ ring_sw(r);
+      const int64_t row = m0 + r < p.M ? m0 + r : m0;  // rows past M: a copy of row m0, never stored
+      lds_direct16(Xb + row * p.ldx + k0 + kc * 8, xring(slot) + r0 * 32);
+    }
+  };
+  auto load_x = [&](TX (&rx)[8], int s) {  // FP32 / FP64 X of stage s into registers
+    const TX *X = reinterpret_cast<const TX *>(p.X);
+    const int64_t k0 = kb + (int64_t)s * BK, col = m0 + xc;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int64_t k = k0 + xk * 8 + e;
-        const bool ok = k < ke && col < p.M;
-        rx[e] = X[(ok ? k : kb) * p.ldx + (ok ? col : m0)];
-      }
-    };
-    auto store_x = [&](const TX (&rx)[8], auto par, int s) {  // ... rounded and transposed into an Xd tile
-      const int64_t k0 = kb + (int64_t)s * BK;
-      const bool cok = m0 + xc < p.M;
-      TX v[8];
+    for (int e = 0; e < 8; ++e) {
+      const int64_t k = k0 + xk * 8 + e;
+      const bool ok = k < ke && col < p.M;
+      rx[e] = X[(ok ? k : kb) * p.ldx + (ok ? col : m0)];
+    }
+  };
+  auto store_x = [&](const TX (&rx)[8], auto par, int s) {  // ... rounded and transposed into an Xd tile
+    const int64_t k0 = kb + (int64_t)s * BK;
+    const bool cok = m0 + xc < p.M;
+    TX v[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (cok && k0 + xk * 8 + e < ke) ? rx[e] : (TX)0;
-      u32x4 w;
-      w.x = pack_bf16(v[0], v[1]);
-      w.y = pack_bf16(v[2], v[3]);
-      w.z = pack_bf16(v[4], v[5]);
-      w.w = pack_bf16(v[6], v[7]);
-      *reinterpret_cast<u32x4 *>(xdbl(par) + xc * LS + xk * 8) = w;
-    };
+    for (int e = 0; e < 8; ++e) v[e] = (cok && k0 + xk * 8 + e < ke) ? rx[e] : (TX)0;
+    u32x4 w;
+    w.x = pack_bf16(v[0], v[1]);
+    w.y = pack_bf16(v[2], v[3]);
+    w.z = pack_bf16(v[4], v[5]);
+    w.w = pack_bf16(v[6], v[7]);
+    *reinterpret_cast<u32x4 *>(xdbl(par) + xc * LS + xk * 8) = w;
+  };
 
-    f32x4 acc[4][WN];
+  f32x4 acc[4][WN];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  auto read_stage = [&](auto slot, auto par, bf16x8 (&a)[4], bf16x8 (&b)[WN]) {  // this wavefront's fragments
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = wm * 64 + i * 16 + (lane & 15);
+      if constexpr (XT) a[i] = *reinterpret_cast<const bf16x8 *>(xring(slot) + r * 32 + ((q ^ ring_sw(r)) * 8));
+      else a[i] = *reinterpret_cast<const bf16x8 *>(xdbl(par) + r * LS + q * 8);
+    }
+    const uint16_t *ls = lring(slot);
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      const int r = wn * 16 * WN + j * 16 + (lane & 15);
+      b[j] = *reinterpret_cast<const bf16x8 *>(ls + r * 32 + ((q ^ ring_sw(r)) * 8));
+    }
+  };
+  auto mfma_stage = [&](const bf16x8 (&a)[4], const bf16x8 (&b)[WN]) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    auto mfma_stage = [&](auto slot, auto par) {
-      bf16x8 a[4], b[WN];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = wm * 64 + i * 16 + (lane & 15);
-        if constexpr (XT) a[i] = *reinterpret_cast<const bf16x8 *>(xring(slot) + r * 32 + ((q ^ ring_sw(r)) * 8));
-        else a[i] = *reinterpret_cast<const bf16x8 *>(xdbl(par) + r * LS + q * 8);
-      }
-      const uint16_t *ls = lring(slot);
-#pragma unroll
-      for (int j = 0; j < WN; ++j) {
-        const int r = wn * 16 * WN + j * 16 + (lane & 15);
-        b[j] = *reinterpret_cast<const bf16x8 *>(ls + r * 32 + ((q ^ ring_sw(r)) * 8));
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < WN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    };
+      for (int j = 0; j < WN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  };
 
-    using I0 = std::integral_constant<int, 0>;
-    using I1 = std::integral_constant<int, 1>;
-    using I2 = std::integral_constant<int, 2>;
-    TX rx0[8], rx1[8];
-    if (nst > 0) {
-      issue(I0{}, 0);
-      if constexpr (!XT) load_x(rx0, 0);
-      if (nst > 1) {
-        issue(I1{}, 1);
-        if constexpr (!XT) load_x(rx1, 1);
-      }
-      if constexpr (!XT) store_x(rx0, I0{}, 0);
-      if (nst > 1) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LIW + XIW) : "memory");
-      else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      __syncthreads();
-    }
-    // Stage s (ring slot s % 3, X parity s % 2): loads of stage s + 2 out,
-    // MFMAs of stage s, stage s + 1 made ready (its X rounded into LDS; its
-    // loads waited for, the two stages just issued left in flight).
-    auto step = [&](auto slot, auto par, int s) {
-      constexpr int SL = decltype(slot)::value, PAR = decltype(par)::value;
-      using Next = std::integral_constant<int, (SL + 1) % 3>;
-      using Ahead = std::integral_constant<int, (SL + 2) % 3>;
-      using NPar = std::integral_constant<int, 1 - PAR>;
-      TX(&rfree)[8] = PAR == 0 ? rx0 : rx1;
-      TX(&rnext)[8] = PAR == 0 ? rx1 : rx0;
-      const bool ahead = s + 2 < nst;
-      if (ahead) {
-        issue(Ahead{}, s + 2);
-        if constexpr (!XT) load_x(rfree, s + 2);
-      }
-      mfma_stage(slot, par);
-      if (s + 1 < nst) {
-        if constexpr (!XT) store_x(rnext, NPar{}, s + 1);
-        if (ahead) asm volatile("s_waitcnt vmcnt(%0)" ::"n"(LIW + XIW) : "memory");
-        else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-      }
-      (void)sizeof(Next);
-    };
-    for (int s = 0; s < nst; s += 6) {
-      step(I0{}, I0{}, s);
-      if (s + 1 < nst) step(I1{}, I1{}, s + 1);
-      if (s + 2 < nst) step(I2{}, I0{}, s + 2);
-      if (s + 3 < nst) step(I0{}, I1{}, s + 3);
-      if (s + 4 < nst) step(I1{}, I0{}, s + 4);
-      if (s + 5 < nst) step(I2{}, I1{}, s + 5);
-    }
-
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < WN; ++j)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + v;
-          const int64_t col = wn * 16 * WN + j * 16 + (lane & 15);
-          if (row < p.M && col < p.N) {
-            if (p.parts) p.parts[(int64_t)z * p.M * p.N + row * p.N + col] = acc[i][j][v];
-            else p.C[row * p.ldc + col] = (double)acc[i][j][v];
-          }
-        }
-    __syncthreads();  // the next tile's first loads go into the ring slots just read
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  TX rx[8];
+  if (nst > 0) {
+    if constexpr (!XT) load_x(rx, 0);
+    issue(I0{}, 0);
+    if (nst > 1) issue(I1{}, 1);
+    if constexpr (!XT) store_x(rx, I0{}, 0);
+    if (nst > 1) asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)" ::"n"(LIW + (XT ? 1 : 0)) : "memory");
+    else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
   }
+  // Stage s (ring slot s % 3, X parity s % 2): the loads of stage s + 1's X
+  // (registers) and stage s + 2's ring copies, this wavefront's fragments of
+  // stage s (with X^T in the ring: first, so that a wait the compiler places
+  // before these reads, for copies into this slot, cannot cover the copies
+  // issued next), the MFMAs of stage s, and stage s + 1 made ready: its X
+  // rounded into LDS, its copies waited for (stage s + 2's left in flight),
+  // a bare barrier (__syncthreads' workgroup fence would also wait for stage
+  // s + 2's copies).
+  auto step = [&](auto slot, auto par, int s) {
+    using Ahead = std::integral_constant<int, (decltype(slot)::value + 2) % 3>;
+    using NPar = std::integral_constant<int, 1 - decltype(par)::value>;
+    const bool next = s + 1 < nst, ahead = s + 2 < nst;
+    bf16x8 fa[4], fb[WN];
+    if constexpr (XT) {
+      read_stage(slot, par, fa, fb);
+      if (ahead) issue(Ahead{}, s + 2);
+    } else {
+      // X's loads before the copies (the wait below then leaves only the
+      // copies in flight), and the fragments after them: read first they
+      // would stay live across the loads' address arithmetic, beyond the
+      // register budget of the widest tile
+      if (next) load_x(rx, s + 1);
+      if (ahead) issue(Ahead{}, s + 2);
+      read_stage(slot, par, fa, fb);
+    }
+    mfma_stage(fa, fb);
+    if (next) {
+      if constexpr (!XT) store_x(rx, NPar{}, s + 1);
+      if (ahead) asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)" ::"n"(LIW + (XT ? 1 : 0)) : "memory");
+      else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+    }
+  };
+  for (int s = 0; s < nst; s += 6) {
+    step(I0{}, I0{}, s);
+    if (s + 1 < nst) step(I1{}, I1{}, s + 1);
+    if (s + 2 < nst) step(I2{}, I0{}, s + 2);
+    if (s + 3 < nst) step(I0{}, I1{}, s + 3);
+    if (s + 4 < nst) step(I1{}, I0{}, s + 4);
+    if (s + 5 < nst) step(I2{}, I1{}, s + 5);
+  }
+
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + v;
+        const int64_t col = wn * 16 * WN + j * 16 + (lane & 15);
+        if (row < p.M && col < p.N) {
+          if (p.parts) p.parts[(int64_t)z * p.M * p.N + row * p.N + col] = acc[i][j][v];
+          else p.C[row * p.ldc + col] = (double)acc[i][j][v];
+        }
+      }
 }
 
 __global__ void k_sum_parts(int64_t M, int64_t N, int splits, const float *__restrict__ parts, double *__restrict__ C,
