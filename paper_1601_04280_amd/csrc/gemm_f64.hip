@@ -214,9 +214,11 @@ __global__ __launch_bounds__(128 * WGM, 1) void k_gemm(GemmK p) {
 
 // Direct global-to-LDS form for FP64 op(A) = A^T with full 128-row tiles
 // (M a multiple of 128, every K extent a multiple of 16, N even, A and B rows
-// 16-byte aligned).  Each K row of a stage's A tile (128 doubles) and B tile
-// (BN doubles) is copied by global_load_lds_dwordx4 instructions of one wave
-// straight into LDS (16 bytes per lane, lanes contiguous).  Three buffers per
+// 16-byte aligned).  Each K row of a stage's A tile (128 doubles, or 128
+// FP32 values of FP32-stored A, widened exactly when read from LDS) and B
+// tile (BN doubles) is copied by global_load_lds_dwordx4 instructions of one
+// wave straight into LDS (16 bytes per lane, lanes contiguous; an FP32 row
+// takes the first 32 lanes).  Three buffers per
 // operand hold stages s (being multiplied), s + 1 (landed) and s + 2 (in
 // flight), so the loads get two stages to land without holding registers;
 // the waits on them are the explicit ones before each barrier.  B columns at
@@ -226,33 +228,38 @@ __global__ __launch_bounds__(128 * WGM, 1) void k_gemm(GemmK p) {
 // lds + 16 i).  A plain device function: the builtin exists only for the
 // device, and the kernel template must also instantiate in the host pass.
 __device__ inline void lds_copy16(const double *g, double *lds) { __builtin_amdgcn_global_load_lds(g, lds, 16, 0, 0); }
+__device__ inline void lds_copy16(const float *g, float *lds) { __builtin_amdgcn_global_load_lds(g, lds, 16, 0, 0); }
 // the same with the nontemporal hint (cache policy bit 1), for an operand
 // that every element of is read once per launch
 __device__ inline void lds_copy16_nt(const double *g, double *lds) { __builtin_amdgcn_global_load_lds(g, lds, 16, 0, 2); }
+__device__ inline void lds_copy16_nt(const float *g, float *lds) { __builtin_amdgcn_global_load_lds(g, lds, 16, 0, 2); }
 
-template <int FN>
+template <int FN, typename TA, typename TC>
 __global__ __launch_bounds__(512, 1) void k_gemm_dma(GemmK p) {
-  typedef Mfma<double> MF;
+  typedef Mfma<TC> MF;  // TC: the compute type, which B is stored in
   constexpr int WGM = 4, FM = 2;
   constexpr int BM = 16 * FM * WGM, BN = 32 * FN;
-  constexpr int H = (BN + 127) / 128;  // copy instructions per B row
-  // a copy instruction writes 128 doubles (64 lanes x 16 bytes) whatever BN
-  // is: B rows are 128 H doubles apart (plus the bank padding), so the lanes
+  constexpr int PI = 64 * 16 / (int)sizeof(TC);  // B elements per copy instruction
+  constexpr int H = (BN + PI - 1) / PI;          // copy instructions per B row
+  // a copy instruction writes PI elements (64 lanes x 16 bytes) whatever BN
+  // is: B rows are PI H elements apart (plus the bank padding), so the lanes
   // past BN write padding rather than the next row
-  constexpr int AS = pad_stride(BM), BS = pad_stride(128 * H);
+  // A rows 144 elements apart: the four k rows of a fragment read start 16
+  // doubles (FP32: 64 bytes of 576) apart in the bank order
+  constexpr int AS = pad_stride(BM), BS = pad_stride(PI * H);
   static_assert(BM == 128 && kBK == 16, "one 1 KB A row per wave instruction, two rows per wave");
   // separate LDS objects, each named statically below: the compiler then
   // knows a read of one buffer does not wait for copies into another
-  __shared__ __align__(16) double As0[kBK * AS], As1[kBK * AS], As2[kBK * AS];
-  __shared__ __align__(16) double Bs0[kBK * BS], Bs1[kBK * BS], Bs2[kBK * BS];
+  __shared__ __align__(16) TA As0[kBK * AS], As1[kBK * AS], As2[kBK * AS];
+  __shared__ __align__(16) TC Bs0[kBK * BS], Bs1[kBK * BS], Bs2[kBK * BS];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = wave % WGM, wn = wave / WGM;
   const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
   const int64_t kb = (int64_t)blockIdx.z * p.Kc;
   const int64_t ke = min(p.K, kb + p.Kc);
-  const double *A = reinterpret_cast<const double *>(p.A);
-  const double *B = reinterpret_cast<const double *>(p.B);
+  const TA *A = reinterpret_cast<const TA *>(p.A);
+  const TC *B = reinterpret_cast<const TC *>(p.B);
 
   typename MF::acc_t acc[FM][FN];
 #pragma unroll
@@ -260,25 +267,29 @@ __global__ __launch_bounds__(512, 1) void k_gemm_dma(GemmK p) {
 #pragma unroll
     for (int j = 0; j < FN; ++j) acc[i][j] = typename MF::acc_t{0, 0, 0, 0};
 
-  auto uniform_ptr = [](const double *q) -> const double * {
+  auto uniform_ptr = [](auto *q) {
     const uint64_t u = reinterpret_cast<uint64_t>(q);
-    return reinterpret_cast<const double *>(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
-                                            (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u));
+    return reinterpret_cast<decltype(q)>(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
+                                         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u));
   };
   // rows 2 wave and 2 wave + 1 of stage k0's tiles into (as, bs)
-  auto copy_stage = [&](double *as, double *bs, int64_t k0) __attribute__((always_inline)) {
+  auto copy_stage = [&](TA *as, TC *bs, int64_t k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int kr = 2 * wave + q;
-      lds_copy16_nt(uniform_ptr(A + (k0 + kr) * p.lda + m0) + 2 * lane, as + kr * AS);
-      const double *brow = uniform_ptr(B + (k0 + kr) * p.ldb + n0);
+      if constexpr (sizeof(TA) == 8) {
+        lds_copy16_nt(uniform_ptr(A + (k0 + kr) * p.lda + m0) + 2 * lane, as + kr * AS);
+      } else if (lane < 32) {  // 128 FP32 values: the first 32 lanes
+        lds_copy16_nt(uniform_ptr(A + (k0 + kr) * p.lda + m0) + 4 * lane, as + kr * AS);
+      }
+      const TC *brow = uniform_ptr(B + (k0 + kr) * p.ldb + n0);
 #pragma unroll
       for (int h = 0; h < H; ++h) {
         // every lane issues (a fixed count of copies per stage); lanes past
         // N or the tile re-read the row's start into columns not stored
-        const int c = 128 * h + 2 * lane;
+        const int c = PI * h + (16 / (int)sizeof(TC)) * lane;
         const int cc = (c < BN && n0 + c < p.N) ? c : 0;
-        lds_copy16(brow + cc, bs + kr * BS + 128 * h);
+        lds_copy16(brow + cc, bs + kr * BS + PI * h);
       }
     }
   };
@@ -290,13 +301,13 @@ __global__ __launch_bounds__(512, 1) void k_gemm_dma(GemmK p) {
   };
   // operand fragments of the four k steps of a stage, in registers; k step
   // kk + 1 is read while k step kk is multiplied
-  double fa[kBK / 4][FM], fb[kBK / 4][FN];
-  auto load_kk = [&](const double *asb, const double *bsb, int kk) __attribute__((always_inline)) {
-    const double *as = asb + wm * 16 * FM + (lane & 15);
-    const double *bs = bsb + wn * 16 * FN + (lane & 15);
+  TC fa[kBK / 4][FM], fb[kBK / 4][FN];
+  auto load_kk = [&](const TA *asb, const TC *bsb, int kk) __attribute__((always_inline)) {
+    const TA *as = asb + wm * 16 * FM + (lane & 15);
+    const TC *bs = bsb + wn * 16 * FN + (lane & 15);
     const int kr = kk * 4 + (lane >> 4);
 #pragma unroll
-    for (int i = 0; i < FM; ++i) fa[kk][i] = as[kr * AS + i * 16];
+    for (int i = 0; i < FM; ++i) fa[kk][i] = (TC)as[kr * AS + i * 16];
 #pragma unroll
     for (int j = 0; j < FN; ++j) fb[kk][j] = bs[kr * BS + j * 16];
   };
@@ -368,7 +379,7 @@ __global__ __launch_bounds__(512, 1) void k_gemm_dma(GemmK p) {
         const int64_t m = m0 + wm * 16 * FM + i * 16 + MF::row(lane, v);
         const int64_t n = n0 + wn * 16 * FN + j * 16 + (lane & 15);
         if (m < p.M && n < p.N) {
-          const double x = acc[i][j][v];
+          const double x = (double)acc[i][j][v];
           if (p.partial) p.C[(int64_t)blockIdx.z * p.cstride + m * p.ldc + n] = x;
           else p.C[m * p.ldc + n] = p.alpha * x;
         }
@@ -463,28 +474,48 @@ static hipError_t launch(const GemmArgs &g, int splits, int64_t Kc, double *part
   const dim3 grid((unsigned)ceil_div(g.M, sh.bm()), (unsigned)ceil_div(g.N, sh.bn()), (unsigned)splits);
   if (g.compute == RLU_F32) {
     if (!g.trans_a || g.gather) return hipErrorInvalidValue;
-    if (g.a_dtype == RLU_F32) return dispatch_shape<float, float, true, false>(sh, grid, k, st);
-    return dispatch_shape<float, double, true, false>(sh, grid, k, st);
-  }
-  if (g.compute != RLU_F64) return hipErrorInvalidValue;
-  if (g.trans_a) {
-    if (g.gather) return hipErrorInvalidValue;
-    if (g.a_dtype == RLU_F32) return dispatch_shape<double, float, true, false>(sh, grid, k, st);
+    const bool f32a = g.a_dtype == RLU_F32;
+    // the direct-to-LDS form: B (FP32) rows copied four values per lane
     const bool full = sh.wgm == 4 && sh.fm == 2 && g.M % 128 == 0 && g.K % kBK == 0 && Kc % kBK == 0 &&
-                      g.N % 2 == 0 && g.lda % 2 == 0 && g.ldb % 2 == 0 &&
+                      g.N % 4 == 0 && g.lda % (f32a ? 4 : 2) == 0 && g.ldb % 4 == 0 &&
                       ((reinterpret_cast<uintptr_t>(g.A) | reinterpret_cast<uintptr_t>(g.B)) & 15) == 0 &&
                       (k.partial || g.beta == 0.0);
     if (full) {
       switch (sh.fn) {
-#define RLU_FN(F)                                                                     \
-  case F:                                                                             \
-    hipLaunchKernelGGL((k_gemm_dma<F>), grid, dim3(512), 0, st, k); \
+#define RLU_FN(F)                                                                            \
+  case F:                                                                                    \
+    if (f32a) hipLaunchKernelGGL((k_gemm_dma<F, float, float>), grid, dim3(512), 0, st, k);   \
+    else hipLaunchKernelGGL((k_gemm_dma<F, double, float>), grid, dim3(512), 0, st, k);       \
     return hipGetLastError();
         RLU_FN(4) RLU_FN(6) RLU_FN(7)
 #undef RLU_FN
         default: break;
       }
     }
+    if (f32a) return dispatch_shape<float, float, true, false>(sh, grid, k, st);
+    return dispatch_shape<float, double, true, false>(sh, grid, k, st);
+  }
+  if (g.compute != RLU_F64) return hipErrorInvalidValue;
+  if (g.trans_a) {
+    if (g.gather) return hipErrorInvalidValue;
+    const bool f32a = g.a_dtype == RLU_F32;
+    const bool full = sh.wgm == 4 && sh.fm == 2 && g.M % 128 == 0 && g.K % kBK == 0 && Kc % kBK == 0 &&
+                      g.N % 2 == 0 && g.lda % (f32a ? 4 : 2) == 0 && g.ldb % 2 == 0 &&
+                      ((reinterpret_cast<uintptr_t>(g.A) | reinterpret_cast<uintptr_t>(g.B)) & 15) == 0 &&
+                      (k.partial || g.beta == 0.0);
+    if (full) {
+      switch (sh.fn) {
+#define RLU_FN(F)                                                                     \
+  case F:                                                                             \
+    if (f32a) hipLaunchKernelGGL((k_gemm_dma<F, float, double>), grid, dim3(512), 0, st, k);   \
+    else hipLaunchKernelGGL((k_gemm_dma<F, double, double>), grid, dim3(512), 0, st, k);       \
+    return hipGetLastError();
+        RLU_FN(4) RLU_FN(6) RLU_FN(7)
+#undef RLU_FN
+        default: break;
+      }
+    }
+    if (f32a) return dispatch_shape<double, float, true, false>(sh, grid, k, st);
     return dispatch_shape<double, double, true, false>(sh, grid, k, st);
   }
   if (g.a_dtype == RLU_F32) {  // FP32 storage, widened exactly (the explicit projection's A)
