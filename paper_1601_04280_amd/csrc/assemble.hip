@@ -103,18 +103,39 @@ __global__ void k_finalize(rlu_info *info, const int32_t *abort_flag) {
 // (perm[j]) holds 1, so that row is skipped.  maxbits[j] receives the
 // column's maximum as the bit pattern of a non-negative double, whose order
 // as an unsigned integer is that of the value (zeroed beforehand).
+// Block: 64 columns (blockIdx.y) x rows_per_block rows; lane = column,
+// wave w takes rows w, w + 4, ...; eight loads in flight per lane, then a
+// reduction over the four waves in LDS and one atomic per column and block.
 __global__ __launch_bounds__(256) void k_gap_colmax(int64_t rows, int l, const double *__restrict__ Lhat,
                                                     const int32_t *__restrict__ perm, int64_t rows_per_block,
                                                     unsigned long long *__restrict__ maxbits) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = blockIdx.y * 64 + lane;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t r1 = r0 + rows_per_block < rows ? r0 + rows_per_block : rows;
-  for (int c = threadIdx.x; c < l; c += blockDim.x) {
-    const int64_t skip = perm[c];
-    double mx = 0.0;
-    for (int64_t r = r0; r < r1; ++r) {
-      const double v = fabs(Lhat[r * l + c]);
-      if (r != skip && v > mx) mx = v;
+  const bool live = c < l;
+  const int64_t skip = live ? perm[c] : -1;
+  const int cc = live ? c : 0;
+  double mx = 0.0;
+  for (int64_t rb = r0 + w; rb < r1; rb += 4 * 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t r = rb + 4 * u;
+      v[u] = (r < r1) ? Lhat[r * l + cc] : 0.0;
     }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t r = rb + 4 * u;
+      const double a = fabs(v[u]);
+      if (r < r1 && r != skip && a > mx) mx = a;
+    }
+  }
+  red[w][lane] = mx;
+  __syncthreads();
+  if (w == 0 && live) {
+    mx = fmax(fmax(red[0][lane], red[1][lane]), fmax(red[2][lane], red[3][lane]));
     if (mx > 0.0) atomicMax(&maxbits[c], (unsigned long long)__double_as_longlong(mx));
   }
 }
@@ -149,9 +170,11 @@ hipError_t launch_pivot_gap(int64_t rows, int l, const double *Lhat, const int32
                             unsigned long long *maxbits, double *out, hipStream_t st) {
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(maxbits), 0u, (int64_t)l * 2, st);
   if (e != hipSuccess) return e;
-  const int64_t rpb = 64;
-  const int blocks = (int)ceil_div(rows, rpb);
-  hipLaunchKernelGGL(k_gap_colmax, dim3(blocks), dim3(256), 0, st, rows, l, Lhat, perm, rpb, maxbits);
+  // 128 rows per block (32 loads per lane), more for tall matrices so that
+  // at most about 1024 blocks meet at each column's atomic
+  const int64_t rpb = align_up(std::max<int64_t>(128, ceil_div(rows, 1024)), 32);
+  const dim3 grid((unsigned)ceil_div(rows, rpb), (unsigned)ceil_div(l, 64));
+  hipLaunchKernelGGL(k_gap_colmax, grid, dim3(256), 0, st, rows, l, Lhat, perm, rpb, maxbits);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_gap_min, dim3(1), dim3(256), 0, st, rows, l, U, maxbits, out);
   return hipGetLastError();

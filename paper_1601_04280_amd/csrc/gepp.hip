@@ -33,6 +33,10 @@ namespace rlu {
 constexpr int kGeppThreads = 256;
 constexpr int kTrailW = 64;
 constexpr int kHdrWords = 4;  // |v| lo, |v| hi, position, row
+// Widest panel whose trailing update streams through k_trail_update; 64-wide
+// panels (rows held one per thread) keep the MFMA GEMM, which measured faster
+// there (2.87 against 2.91 ms per 16384 x 8192 decomposition).
+constexpr int kTrailMaxK = 32;
 
 struct GeppKArgs {
   int64_t M;
@@ -549,6 +553,65 @@ __global__ __launch_bounds__(256) void k_u12_mfma(int l, int j0, int nbp, const 
   }
 }
 
+// Trailing update of a tall panel, C[M x N] -= L[M x KB] U[KB x N] (the
+// product in the same row-major layout as the GEMM's): a rank-KB update is
+// a streaming read-modify-write of C with KB flops per byte at most, so
+// instead of MFMA tiles, lane j of a wave keeps column j's KB entries of U
+// in registers and the wave walks a run of rows, eight at a time; each row's
+// KB multipliers are uniform across the wave (scalar loads).
+template <int KB>
+__global__ __launch_bounds__(256) void k_trail_update(int64_t M, int N, const double *__restrict__ L, int64_t ldl,
+                                                      const double *__restrict__ U, int64_t ldu,
+                                                      double *__restrict__ C, int64_t ldc, int64_t rows_per_wave) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int c = blockIdx.y * 64 + lane;
+  const bool live = c < N;
+  const int cc = live ? c : 0;
+  double u[KB];
+#pragma unroll
+  for (int k = 0; k < KB; ++k) u[k] = U[(int64_t)k * ldu + cc];
+  const int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * rows_per_wave;
+  const int64_t r1 = r0 + rows_per_wave < M ? r0 + rows_per_wave : M;
+  constexpr int RB = 8;  // rows per batch: their loads are in flight together
+  for (int64_t r = r0; r < r1; r += RB) {
+    double cv[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) cv[i] = (r + i < r1) ? C[(r + i) * ldc + cc] : 0.0;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      if (r + i < r1) {
+        const double *lr = L + (r + i) * ldl;
+        // two interleaved partial sums halve the dependent chain
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < KB; k += 2) {
+          s0 = __builtin_fma(lr[k], u[k], s0);
+          s1 = __builtin_fma(lr[k + 1], u[k + 1], s1);
+        }
+        cv[i] -= s0 + s1;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+      if (r + i < r1 && live) C[(r + i) * ldc + c] = cv[i];
+  }
+}
+
+static hipError_t launch_trail_update(int64_t M, int N, int K, const double *L, int64_t ldl, const double *U,
+                                      int64_t ldu, double *C, int64_t ldc, hipStream_t st) {
+  // enough waves for about eight per SIMD, runs of whole row batches
+  const int64_t rpw = align_up(std::max<int64_t>(8, ceil_div(M, (int64_t)256 * 4 * 8)), 8);
+  const dim3 grid((unsigned)ceil_div(M, 4 * rpw), (unsigned)ceil_div(N, 64));
+  switch (K) {
+    case 8: hipLaunchKernelGGL(k_trail_update<8>, grid, dim3(256), 0, st, M, N, L, ldl, U, ldu, C, ldc, rpw); break;
+    case 16: hipLaunchKernelGGL(k_trail_update<16>, grid, dim3(256), 0, st, M, N, L, ldl, U, ldu, C, ldc, rpw); break;
+    case 32: hipLaunchKernelGGL(k_trail_update<32>, grid, dim3(256), 0, st, M, N, L, ldl, U, ldu, C, ldc, rpw); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 typedef void (*GeppKernel)(GeppKArgs);
 
 static GeppKernel gepp_kernel(int rpt) {
@@ -665,6 +728,12 @@ hipError_t launch_gepp(int64_t rows, int cols, const double *X, int64_t ldx, dou
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // trailing update: Wk[:, j1:] -= Lhat[:, j0:j1] U[j0:j1, j1:]
+    if (nbp <= kTrailMaxK) {
+      if ((e = launch_trail_update(rows, J2, nbp, Lhat + j0, cols, U + (size_t)j0 * cols + j1, cols, Wk + j1, cols,
+                                   st)) != hipSuccess)
+        return e;
+      continue;
+    }
     GemmArgs gm{};
     gm.M = rows; gm.N = J2; gm.K = nbp;
     gm.A = Lhat + j0; gm.lda = cols; gm.a_dtype = RLU_F64; gm.trans_a = false;
