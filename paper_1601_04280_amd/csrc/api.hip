@@ -429,8 +429,11 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   double *Uy = out->Uy ? out->Uy : at<double>(ws, fp.Uy);
   sm.begin(RLU_STAGE_LU_Y, st);
   const bool exclusive = (p->flags & RLU_FLAG_EXCLUSIVE) != 0 || (env && env->exclusive);
+  // Y is not read again: when it is the library's scratch (no Y output, or
+  // the gathered columns of the rank-k form), the LU's updates run in it
+  const bool y_scratch = out->Y == nullptr || truncated(p);
   e = launch_gepp(m, l, Y, ldy, Lhat, Uy, out->perm_r, out->ipiv_r, at<void>(ws, fp.slots), abort_flag, info,
-                  0, fp.py, exclusive, st);
+                  0, fp.py, exclusive, y_scratch, st);
   if (e != hipSuccess) return hip_fail(e, "row-pivoted LU launch");
   sm.end(RLU_STAGE_LU_Y, st);
 
@@ -570,7 +573,7 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
   double *Lph = at<double>(ws, fp.Lph), *Up = at<double>(ws, fp.Up), *Lt = at<double>(ws, fp.Lt);
   sm.begin(RLU_STAGE_LU_B, st);
   e = launch_gepp(n, l, Bt, l, Lph, Up, out->perm_c, out->ipiv_c, at<void>(ws, fp.slots), abort_flag, info, 1,
-                  fp.pb, exclusive, st);
+                  fp.pb, exclusive, true, st);
   if (e != hipSuccess) return hip_fail(e, "column-pivoted LU launch");
   sm.end(RLU_STAGE_LU_B, st);
   sm.begin(RLU_STAGE_ASSEMBLE, st);
@@ -824,7 +827,7 @@ rlu_status rlu_tall_lu(rlu_ctx *ctx, const double *X, int64_t rows, int64_t cols
   if ((e = launch_fill_u32(reinterpret_cast<uint32_t *>(info), 0u, sizeof(rlu_info) / 4, s)) != hipSuccess)
     return hip_fail(e, "fill");
   e = launch_gepp(rows, (int)cols, X, ldx, Lhat, U, perm, ipiv, at<void>(ws, o_slots),
-                  reinterpret_cast<int32_t *>(ctl + 1), info, 0, gp, false, s);
+                  reinterpret_cast<int32_t *>(ctl + 1), info, 0, gp, false, false, s);
   if (e != hipSuccess) return hip_fail(e, "tall LU launch");
   if ((e = launch_pivot_gap(rows, (int)cols, Lhat, perm, U, at<unsigned long long>(ws, o_gaps), &info->min_gap_y,
                             s)) != hipSuccess ||

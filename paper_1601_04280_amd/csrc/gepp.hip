@@ -665,7 +665,7 @@ size_t gepp_workspace_bytes(int64_t rows, int cols, const GeppPlan &plan) {
 
 hipError_t launch_gepp(int64_t rows, int cols, const double *X, int64_t ldx, double *Lhat, double *U,
                        int32_t *perm, int32_t *ipiv, void *ws, int32_t *abort_flag, rlu_info *info,
-                       int which, const GeppPlan &plan, bool exclusive, hipStream_t st) {
+                       int which, const GeppPlan &plan, bool exclusive, bool x_scratch, hipStream_t st) {
   GeppKernel k = gepp_kernel(64 / plan.nb);
   if (!k) return hipErrorInvalidValue;
   char *w = reinterpret_cast<char *>(ws);
@@ -679,10 +679,16 @@ hipError_t launch_gepp(int64_t rows, int cols, const double *X, int64_t ldx, dou
   // the tagged words must start from zero for this factorization
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(slots), 0u, (int64_t)(slot_bytes / 4), st);
   if (e != hipSuccess) return e;
+  // the matrix whose trailing columns the updates rewrite: X itself when it
+  // is the library's scratch, else a working copy
+  double *work = nullptr;
   const double *src = X;
   int64_t ldsrc = ldx;
-  if (plan.multi) {  // trailing columns are updated in place in a working copy
+  if (plan.multi && x_scratch) {
+    work = const_cast<double *>(X);
+  } else if (plan.multi) {
     if ((e = launch_copy_rows(rows, cols, X, ldx, Wk, cols, st)) != hipSuccess) return e;
+    work = Wk;
     src = Wk;
     ldsrc = cols;
   }
@@ -727,9 +733,9 @@ hipError_t launch_gepp(int64_t rows, int cols, const double *X, int64_t ldx, dou
       default: return hipErrorInvalidValue;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    // trailing update: Wk[:, j1:] -= Lhat[:, j0:j1] U[j0:j1, j1:]
+    // trailing update: work[:, j1:] -= Lhat[:, j0:j1] U[j0:j1, j1:]
     if (nbp <= kTrailMaxK) {
-      if ((e = launch_trail_update(rows, J2, nbp, Lhat + j0, cols, U + (size_t)j0 * cols + j1, cols, Wk + j1, cols,
+      if ((e = launch_trail_update(rows, J2, nbp, Lhat + j0, cols, U + (size_t)j0 * cols + j1, cols, work + j1, ldsrc,
                                    st)) != hipSuccess)
         return e;
       continue;
@@ -738,7 +744,7 @@ hipError_t launch_gepp(int64_t rows, int cols, const double *X, int64_t ldx, dou
     gm.M = rows; gm.N = J2; gm.K = nbp;
     gm.A = Lhat + j0; gm.lda = cols; gm.a_dtype = RLU_F64; gm.trans_a = false;
     gm.B = U + (size_t)j0 * cols + j1; gm.ldb = cols;
-    gm.C = Wk + j1; gm.ldc = cols;
+    gm.C = work + j1; gm.ldc = ldsrc;
     gm.alpha = -1.0; gm.beta = 1.0;
     if ((e = gemm_f64(gm, st)) != hipSuccess) return e;
   }

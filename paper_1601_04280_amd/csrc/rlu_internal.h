@@ -129,9 +129,11 @@ size_t gepp_workspace_bytes(int64_t rows, int cols, const GeppPlan &plan);
 // (gepp_workspace_bytes); abort_flag is a zeroed word shared by the launches
 // of one call.  exclusive: the panel kernels are ordinary launches (the
 // caller guarantees an otherwise idle device), else cooperative ones.
+// x_scratch: X is the library's own scratch and may be overwritten (the
+// trailing updates then run in place, without the working copy).
 hipError_t launch_gepp(int64_t rows, int cols, const double *X, int64_t ldx, double *Lhat, double *U,
                        int32_t *perm, int32_t *ipiv, void *ws, int32_t *abort_flag, rlu_info *info,
-                       int which, const GeppPlan &plan, bool exclusive, hipStream_t st);
+                       int which, const GeppPlan &plan, bool exclusive, bool x_scratch, hipStream_t st);
 
 // ---- GEMM on MFMA ----------------------------------------------------------------
 // C (M x N, ldc, FP64) = alpha * op(A) * op(B) + beta * C, or split-K partials.

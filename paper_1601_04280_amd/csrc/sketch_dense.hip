@@ -10,6 +10,8 @@
 // stream overlaps the transform; the twiddles and the selection live in LDS
 // for that reason (a global load inside the transform would wait for the
 // prefetch).  Longer rows stream their remainder 16 loads per thread deep.
+#include <type_traits>
+
 #include "fft_lds.h"
 #include "rlu_device.h"
 #include "rlu_internal.h"
@@ -352,8 +354,8 @@ __host__ __device__ inline int padc(int i) { return i + (i >> 4); }
 
 // In-place decimation-in-frequency transform of N <= 2048 complex values by
 // one wave (kernel e^{-2 pi i / N}).  Passes of radix 16 while the block size
-// M is at least 16, then radix 4, or radix 2 then 4, or 2, for what is left
-// (1024 = 16 16 4).  A pass of radix R over blocks of size M = R S computes,
+// M is at least 16, then one pass of radix 8, 4 or 2 for what is left
+// (1024 = 16 16 4, 2048 = 16 16 8).  A pass of radix R over blocks of size M = R S computes,
 // for each block start g and 0 <= j < S, from a_r = z[g + j + r S]:
 //   y_m = (sum_r a_r e^{-2 pi i r m / R}) w^{j m},  w = e^{-2 pi i / M},
 // and stores y_m back at z[g + j + m S].  A butterfly reads and writes the
@@ -413,15 +415,28 @@ __device__ inline void fft_wave(double2 *z, int N, const TwSplit &twf, int lane)
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the next pass reads other lanes' writes
   }
-  if (M == 8) {  // radix 2 over blocks of 8 (S = 4), then radix 4 below
-    for (int b = lane; b < (N >> 1); b += 64) {
-      const int jj = b & 3, g = (b >> 2) * 8;
-      const double2 a0 = z[padc(g + jj)], a1 = z[padc(g + jj + 4)];
-      z[padc(g + jj)] = cadd(a0, a1);
-      z[padc(g + jj + 4)] = cmul(csub(a0, a1), twf(jj * (N / 8)));
+  if (M == 8) {  // radix 8 over blocks of 8 (S = 1: no twiddles), as even and odd 4-point DFTs
+    constexpr double R2 = 0.70710678118654752;
+    for (int b = lane; b < (N >> 3); b += 64) {
+      double2 a[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) a[r] = z[padc(8 * b + r)];
+      dft4(a[0], a[2], a[4], a[6]);
+      dft4(a[1], a[3], a[5], a[7]);
+      const double2 o1 = cmul(a[3], make_double2(R2, -R2));   // w8^1
+      const double2 o2 = make_double2(a[5].y, -a[5].x);       // w8^2 = -i
+      const double2 o3 = cmul(a[7], make_double2(-R2, -R2));  // w8^3
+      z[padc(8 * b)] = cadd(a[0], a[1]);
+      z[padc(8 * b + 4)] = csub(a[0], a[1]);
+      z[padc(8 * b + 1)] = cadd(a[2], o1);
+      z[padc(8 * b + 5)] = csub(a[2], o1);
+      z[padc(8 * b + 2)] = cadd(a[4], o2);
+      z[padc(8 * b + 6)] = csub(a[4], o2);
+      z[padc(8 * b + 3)] = cadd(a[6], o3);
+      z[padc(8 * b + 7)] = csub(a[6], o3);
     }
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    M = 4;
+    return;
   }
   if (M == 4) {  // radix 4 over blocks of 4 (S = 1: no twiddles)
     for (int b = lane; b < (N >> 2); b += 64) {
@@ -452,11 +467,7 @@ __host__ __device__ inline int dif_pos(int k, int N) {
     p += (k & 15) * (M >> 4);
     k >>= 4;
   }
-  if (M == 8) {
-    p += (k & 1) * 4;
-    k >>= 1;
-    M = 4;
-  }
+  if (M == 8) return p + (k & 7);
   if (M == 4) p += k & 3;
   else if (M == 2) p += k & 1;
   return p;
@@ -496,13 +507,16 @@ template <> struct WsVec<float> {
   static constexpr int kW = 4, kU = 4;
 };
 
-template <typename T>
-__global__ __launch_bounds__(kWsThreads, 4) void k_sketch_ws(int64_t m, int64_t n, const T *__restrict__ A, int64_t lda,
+// SPLIT (read-out by the streaming waves): registers for two blocks per CU,
+// which is what the LDS of the long transforms that take it allows anyway
+template <typename T, int SPLIT>
+__global__ __launch_bounds__(kWsThreads, SPLIT ? 2 : 4) void k_sketch_ws(int64_t m, int64_t n, const T *__restrict__ A, int64_t lda,
                                                           int s, int log2N, int l, const uint32_t *__restrict__ code,
                                                           const int32_t *__restrict__ sel,
                                                           const double2 *__restrict__ twf,
                                                           const double2 *__restrict__ twp, double *__restrict__ Y,
                                                           int64_t ldy, uint32_t *__restrict__ next_row, int hadamard) {
+  constexpr bool split_out = SPLIT != 0;
   typedef typename WsVec<T>::V VT;
   typedef typename WsVec<T>::C CT;
   constexpr int W = WsVec<T>::kW, U = WsVec<T>::kU;
@@ -530,11 +544,11 @@ __global__ __launch_bounds__(kWsThreads, 4) void k_sketch_ws(int64_t m, int64_t 
   // Rows: the block's first K rows strided by the grid (K G <= 3m/4), then
   // rows from a global counter as blocks go (blocks sharing a CU progress at
   // different rates; one counter for all rows would serialise on its
-  // address).  Fetched two ahead into a ring of four LDS slots: slot
-  // (it + 2) & 3 is written in iteration it and read from iteration it + 1
-  // on; iteration it reads slots it, it - 1 and it + 1.  A block's rows
+  // address).  Fetched two ahead into a ring of eight LDS slots: slot
+  // (it + 2) & 7 is written in iteration it and read from iteration it + 1
+  // on; iteration it reads slots it - 2 .. it + 1.  A block's rows
   // increase, so once a slot holds m or more, all later ones do.
-  __shared__ int64_t s_row[4];
+  __shared__ int64_t s_row[8];
   const int64_t G = gridDim.x, K = (m / G) * 3 / 4;
   auto fetch = [&](int64_t j) -> int64_t {
     if (j < K) return (int64_t)blockIdx.x + j * G;
@@ -580,11 +594,46 @@ __global__ __launch_bounds__(kWsThreads, 4) void k_sketch_ws(int64_t m, int64_t 
       }
     }
   };
+  // A row's l coordinates from its transformed buffer z, by nt threads
+  // (index t0), UR coordinates per thread at a time with their loads first;
+  // then (clear) the buffer zeroed for the next row.
+  auto readout = [&](auto ur, double2 *z, int64_t row, int t0, int nt) __attribute__((always_inline)) {
+    constexpr int UR = decltype(ur)::value;
+    double *yrow = Y + row * ldy;
+    if (hadamard) {
+      const double *zr = reinterpret_cast<const double *>(z);
+      for (int q = t0; q < l; q += nt) yrow[q] = zr[hpad(code_s[q].x)] * rs;
+    } else {
+      for (int q0 = 0; q0 < l; q0 += UR * nt) {
+        int2 cd[UR];
+#pragma unroll
+        for (int u = 0; u < UR; ++u) cd[u] = code_s[min(q0 + t0 + nt * u, l - 1)];
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+          const int q = q0 + t0 + nt * u;
+          const double v = coord_value(z, cd[u], tp, rs, r2s);
+          if (q < l) yrow[q] = v;
+        }
+      }
+    }
+  };
+  auto clear = [&](double2 *z, int t0, int nt) __attribute__((always_inline)) {
+    for (int i = t0; i < NP; i += nt) z[i] = make_double2(0.0, 0.0);
+  };
   // The two roles run separate row loops with the same number of block
-  // barriers (they read the same slots), one per row: the roles' registers are never live
+  // barriers (they read the same slots), one per row, or two with
+  // split_out: the roles' registers are never live
   // at the same time.  Thread indices are made opaque to loop-invariant code
   // motion, which would otherwise hoist every lane mask and offset of the
   // unrolled loops out of the row loop (and spill them).
+  // Iteration it streams row cur into buffer it & 1 and transforms row prev
+  // in buffer (it - 1) & 1.  The transform wave also reads prev's
+  // coordinates out and clears its buffer, unless split_out (a transform
+  // longer than a row's stream): then the streaming waves do that for row
+  // prev2 at the start of the next iteration but one, before they stream
+  // into the same buffer, with a barrier after the read-out (the three waves
+  // read what the others clear) and one after the clearing: three barriers
+  // per row.
   // the transform role rotates with the block index, so that the transform
   // waves of the blocks sharing a CU sit on different SIMDs
   const int fw = (int)(blockIdx.x & 3);
@@ -593,11 +642,19 @@ __global__ __launch_bounds__(kWsThreads, 4) void k_sketch_ws(int64_t m, int64_t 
   if (wave != fw) {
     if (s_row[0] < m) load(va, ca, s_row[0], 0, sid);
     for (int it = 0;; ++it) {
-      const int64_t cur = s_row[it & 3], prev = it ? s_row[(it - 1) & 3] : m;
-      if (cur >= m && prev >= m) break;
+      const int64_t cur = s_row[it & 7], prev = it ? s_row[(it - 1) & 7] : m;
+      const int64_t prev2 = (split_out && it >= 2) ? s_row[(it - 2) & 7] : m;
+      if (cur >= m && prev >= m && prev2 >= m) break;
       int tx = sid;
       asm volatile("" : "+v"(tx));
-      if (tx == 0) s_row[(it + 2) & 3] = s_row[(it + 1) & 3] < m ? fetch(it + 2) : m;
+      if (tx == 0) s_row[(it + 2) & 7] = s_row[(it + 1) & 7] < m ? fetch(it + 2) : m;
+      if (split_out) {
+        double2 *zb = (it & 1) ? lds2 + NP : lds2;
+        if (prev2 < m) readout(std::integral_constant<int, 1>(), zb, prev2, tx, kWsSem);
+        __syncthreads();
+        if (prev2 < m) clear(zb, tx, kWsSem);
+        __syncthreads();
+      }
       if (cur < m) {  // stream row cur into buffer it & 1
         double *y0 = reinterpret_cast<double *>((it & 1) ? lds2 + NP : lds2);
         for (int64_t k = 0; k < nch; k += 2) {
@@ -608,41 +665,32 @@ __global__ __launch_bounds__(kWsThreads, 4) void k_sketch_ws(int64_t m, int64_t 
             scatter(vb, cb, y0, k + 1, tx);
           }
         }
-        const int64_t nxt = s_row[(it + 1) & 3];
+        const int64_t nxt = s_row[(it + 1) & 7];
         if (nxt < m) load(va, ca, nxt, 0, tx);
       }
       __syncthreads();
     }
   } else {
     for (int it = 0;; ++it) {
-      const int64_t cur = s_row[it & 3], prev = it ? s_row[(it - 1) & 3] : m;
-      if (cur >= m && prev >= m) break;
+      const int64_t cur = s_row[it & 7], prev = it ? s_row[(it - 1) & 7] : m;
+      const int64_t prev2 = (split_out && it >= 2) ? s_row[(it - 2) & 7] : m;
+      if (cur >= m && prev >= m && prev2 >= m) break;
       int tx = tid;
       asm volatile("" : "+v"(tx));
-      if (prev < m) {  // transform row prev (buffer (it - 1) & 1), write it, clear the buffer
+      if (split_out) {
+        __syncthreads();
+        __syncthreads();
+      }
+      if (prev < m) {  // transform row prev (buffer (it - 1) & 1)
         double2 *z = ((it - 1) & 1) ? lds2 + NP : lds2;
         const int ln = tx & 63;
-        double *yrow = Y + prev * ldy;
-        if (hadamard) {  // in place on the bucket sums, natural order
-          double *zr = reinterpret_cast<double *>(z);
-          fwht_wave(zr, log2N + 1, ln);
-          for (int q = ln; q < l; q += 64) yrow[q] = zr[hpad(code_s[q].x)] * rs;
-        } else {
-          fft_wave(z, N, tf, ln);
-          for (int q0 = 0; q0 < l; q0 += 256) {  // four coordinates per lane: all loads first
-            int2 cd[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) cd[u] = code_s[min(q0 + ln + 64 * u, l - 1)];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const int q = q0 + ln + 64 * u;
-              const double v = coord_value(z, cd[u], tp, rs, r2s);
-              if (q < l) yrow[q] = v;
-            }
-          }
+        if (hadamard) fwht_wave(reinterpret_cast<double *>(z), log2N + 1, ln);  // in place, natural order
+        else fft_wave(z, N, tf, ln);
+        if (!split_out) {
+          readout(std::integral_constant<int, 4>(), z, prev, ln, 64);
+          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // one wave: its reads before its clearing
+          clear(z, ln, 64);
         }
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        for (int i = ln; i < NP; i += 64) z[i] = make_double2(0.0, 0.0);
       }
       __syncthreads();
     }
@@ -682,8 +730,14 @@ hipError_t launch_sketch_dense(int64_t m, int64_t n, const void *A, int dtype, i
     // blocks per CU as the runtime resolves them (registers, LDS and its
     // allocation granularity): a grid of resident blocks, each taking every
     // grid-th row, with no second round of blocks
+    // the read-out goes to the streaming waves when the transform outlasts a
+    // row's stream: s / 2 complex points against the row's bytes, as measured
+    // (N = 2048 took 13 us per row against 7 us for a 64 KB row; N = 1024
+    // took 6 us against 8 us)
+    const bool split = (int64_t)(s / 2) * 32 >= n * (dtype == RLU_F64 ? 8 : 4);
+    const void *kfn = dtype == RLU_F64 ? (split ? (const void *)k_sketch_ws<double, 1> : (const void *)k_sketch_ws<double, 0>)
+                                       : (split ? (const void *)k_sketch_ws<float, 1> : (const void *)k_sketch_ws<float, 0>);
     int per_cu = 0;
-    const void *kfn = dtype == RLU_F64 ? (const void *)k_sketch_ws<double> : (const void *)k_sketch_ws<float>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kWsThreads, lds) != hipSuccess || per_cu < 1) {
       (void)hipGetLastError();
       per_cu = 1;
@@ -691,12 +745,17 @@ hipError_t launch_sketch_dense(int64_t m, int64_t n, const void *A, int dtype, i
     per_cu = std::min(per_cu, 4);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(m, (int64_t)num_cu * per_cu));
     const int log2N = ilog2_exact(s / 2);
-    if (dtype == RLU_F64)
-      hipLaunchKernelGGL(k_sketch_ws<double>, dim3(grid), dim3(kWsThreads), lds, st, m, n, (const double *)A, lda, s,
-                         log2N, l, code, sel, twf, twp, Y, ldy, row_counter, had);
-    else
-      hipLaunchKernelGGL(k_sketch_ws<float>, dim3(grid), dim3(kWsThreads), lds, st, m, n, (const float *)A, lda, s,
-                         log2N, l, code, sel, twf, twp, Y, ldy, row_counter, had);
+#define RLU_WS(TT, SP)                                                                                         \
+  hipLaunchKernelGGL((k_sketch_ws<TT, SP>), dim3(grid), dim3(kWsThreads), lds, st, m, n, (const TT *)A, lda, s, \
+                     log2N, l, code, sel, twf, twp, Y, ldy, row_counter, had)
+    if (dtype == RLU_F64) {
+      if (split) RLU_WS(double, 1);
+      else RLU_WS(double, 0);
+    } else {
+      if (split) RLU_WS(float, 1);
+      else RLU_WS(float, 0);
+    }
+#undef RLU_WS
     return hipGetLastError();
   }
   const size_t lds = sketch_lds_bytes(s, l);
@@ -783,8 +842,10 @@ void sketch_dense_set_attrs() {
   hipFuncSetAttribute((const void *)k_sketch_ordered<float>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   hipFuncSetAttribute((const void *)k_ordered_tables, hipFuncAttributeMaxDynamicSharedMemorySize, kOrdMaxChunk * 4);
   const int ws_bytes = (int)sketch_ws_lds_bytes(2 * kWsMaxN, 1024);
-  hipFuncSetAttribute((const void *)k_sketch_ws<double>, hipFuncAttributeMaxDynamicSharedMemorySize, ws_bytes);
-  hipFuncSetAttribute((const void *)k_sketch_ws<float>, hipFuncAttributeMaxDynamicSharedMemorySize, ws_bytes);
+  hipFuncSetAttribute((const void *)k_sketch_ws<double, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, ws_bytes);
+  hipFuncSetAttribute((const void *)k_sketch_ws<double, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, ws_bytes);
+  hipFuncSetAttribute((const void *)k_sketch_ws<float, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, ws_bytes);
+  hipFuncSetAttribute((const void *)k_sketch_ws<float, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, ws_bytes);
 #define RLU_ATTR(T, P) \
   hipFuncSetAttribute((const void *)k_sketch_dense<T, P>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   RLU_ATTR(double, 4) RLU_ATTR(double, 8) RLU_ATTR(double, 16)
