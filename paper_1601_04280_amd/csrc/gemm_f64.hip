@@ -457,9 +457,12 @@ static hipError_t dispatch_shape(const Shape &sh, dim3 grid, GemmK k, hipStream_
   return hipErrorInvalidValue;
 }
 
-static hipError_t launch(const GemmArgs &g, int splits, int64_t Kc, double *parts, hipStream_t st) {
+// wide: 128-row tiles of eight waves whatever M (see gemm_f64_splitk)
+static hipError_t launch(const GemmArgs &g, int splits, int64_t Kc, double *parts, hipStream_t st,
+                         bool wide = false) {
   if (g.trans_b) return hipErrorInvalidValue;
-  const Shape sh = pick_shape(g.M, g.N, g.K);
+  Shape sh = pick_shape(g.M, g.N, g.K);
+  if (wide) sh.wgm = 4;
   GemmK k;
   k.M = g.M; k.N = g.N; k.K = g.K;
   k.A = g.A; k.lda = g.lda; k.gather = g.gather;
@@ -554,19 +557,49 @@ size_t gemm_f64_splitk_scratch(int64_t M, int64_t N, int splits) {
   return splits > 1 ? align_up((size_t)splits * M * N * sizeof(double), 256) : 0;
 }
 
-hipError_t gemm_f64_splitk(const GemmArgs &g, int splits, double *parts, hipStream_t st) {
-  if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  if (splits <= 1 || parts == nullptr) return gemm_f64(g, st);
+static hipError_t splitk_run(const GemmArgs &g, int splits, double *parts, hipStream_t st, bool wide) {
   int64_t Kc = ceil_div(g.K, splits);
   Kc = ceil_div(Kc, kBK) * kBK;
   const int used = (int)ceil_div(g.K, Kc);
-  hipError_t e = launch(g, used, Kc, parts, st);
+  hipError_t e = launch(g, used, Kc, parts, st, wide);
   if (e != hipSuccess) return e;
   const int64_t total = g.M * g.N;
   const int blocks = (int)std::min<int64_t>(4096, ceil_div(total, 256));
   hipLaunchKernelGGL(k_splitk_reduce, dim3(std::max(1, blocks)), dim3(256), 0, st, g.M, g.N, used,
                      parts, g.C, g.ldc, g.alpha, g.beta);
   return hipGetLastError();
+}
+
+hipError_t gemm_f64_splitk(const GemmArgs &g, int splits, double *parts, hipStream_t st) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  if (splits <= 1 || parts == nullptr) return gemm_f64(g, st);
+  // A^T B with at least 512 rows that are not whole 128-row tiles (the Gram
+  // matrix of l = 520, for one): the whole tiles on the direct-to-LDS kernel
+  // with 128-row tiles, then the rows left on the general one, through the
+  // same partials one after the other (the stream orders them).  As one
+  // product on 64-row tiles the 520 x 520 x 32768 Gram matrix ran at
+  // 26 TF/s.
+  if (g.trans_a && g.compute == RLU_F64 && !g.gather && g.M >= 512 && g.M % 128 != 0 && g.K >= 1024) {
+    const int64_t Mf = g.M / 128 * 128;
+    const size_t esz = g.a_dtype == RLU_F32 ? 4 : 8;
+    GemmArgs a = g, b = g;
+    a.M = Mf;
+    b.M = g.M - Mf;
+    b.A = static_cast<const char *>(g.A) + (size_t)Mf * esz;  // A is K x M: columns Mf ..
+    b.C = g.C + Mf * g.ldc;
+    // K splits for one round of the wide tiles (at most the caller's count,
+    // which sized the partials)
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      ncu = 256;
+    const Shape sh = pick_shape(Mf, g.N, g.K);
+    const int64_t tiles = (Mf / 128) * ceil_div(g.N, (int64_t)sh.bn());
+    const int sa = (int)std::max<int64_t>(1, std::min<int64_t>(splits, ncu / std::max<int64_t>(1, tiles)));
+    hipError_t e = splitk_run(a, sa, parts, st, true);
+    if (e != hipSuccess) return e;
+    return splitk_run(b, splits, parts, st, false);
+  }
+  return splitk_run(g, splits, parts, st, false);
 }
 
 }  // namespace rlu
