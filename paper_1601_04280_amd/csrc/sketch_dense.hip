@@ -340,10 +340,12 @@ hipError_t launch_sketch_ordered(int64_t m, int64_t n, const void *A, int dtype,
 // s = 4096, whose two row buffers take 70 KB of LDS).  Three waves
 // stream row r with 16-byte loads, a chunk of the row in flight per thread,
 // and scatter it into LDS buffer r & 1; the fourth meanwhile transforms row
-// r - 1 in the other buffer,
-// writes its l coordinates and clears the buffer.  One block barrier per row,
-// and the transform (by one wave, in place, decimation in frequency, with
-// the split twiddle tables in LDS) is off the row stream's critical path.
+// r - 1 in the other buffer, writes its l coordinates and clears the
+// buffer.  One block barrier per row, and the transform (by one wave, in
+// place, decimation in frequency, with the split twiddle tables in LDS) is
+// off the row stream's critical path.  Where the transform would outlast a
+// row's stream, the streaming waves take over the read-out and clearing
+// (SPLIT, three barriers per row; see the kernel).
 // Complex index i is stored at i + i / 16 (one pad per 16) so that the
 // passes' strided accesses spread over the LDS banks.
 constexpr int kWsSem = 192;                 // streaming threads (three waves)
