@@ -280,22 +280,28 @@ __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
     const uint64_t *hpp = a.hdr + (size_t)(j & 1) * kHdrWords * a.HS;
     if (wave == 0) {  // all headers of step j -> winner (G <= 256: <= 4 slots per lane)
       const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-      uint64_t h0[4], h1[4], h2[4], h3[4] = {0, 0, 0, 0};
+      uint64_t h0[4] = {0, 0, 0, 0}, h1[4] = {0, 0, 0, 0}, h2[4] = {0, 0, 0, 0}, h3[4] = {0, 0, 0, 0};
+      const int ng = (G + 63) >> 6;  // slot groups (uniform)
       int ok = 1;
       for (uint32_t it = 1;; ++it) {
-        int ready = 1;
+        // every group's loads first (lanes past G load nothing), then the
+        // tag checks: a round is one memory round trip at any G
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
-          const int sidx = lane + 64 * qq;
-          if (sidx < G) {
-            const uint64_t *hq = hpp + sidx;
+          if (qq < ng && lane + 64 * qq < G) {
+            const uint64_t *hq = hpp + lane + 64 * qq;
             h0[qq] = tw_get(hq);
             h1[qq] = tw_get(hq + a.HS);
             h2[qq] = tw_get(hq + 2 * a.HS);
             h3[qq] = tw_get(hq + 3 * a.HS);
-            ready &= (tw_tag(h0[qq]) == tag) & (tw_tag(h1[qq]) == tag) & (tw_tag(h2[qq]) == tag) &
-                     (tw_tag(h3[qq]) == tag);
           }
+        }
+        int ready = 1;
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+          if (qq < ng)
+            ready &= (lane + 64 * qq >= G) | ((tw_tag(h0[qq]) == tag) & (tw_tag(h1[qq]) == tag) &
+                                              (tw_tag(h2[qq]) == tag) & (tw_tag(h3[qq]) == tag));
         }
         if (__all(ready)) break;
         if ((it & 255) == 0 && !poll_ok(t0, tmo, a.abort_flag)) { ok = 0; break; }
