@@ -74,6 +74,30 @@ def test_alone_equals_mix():
         same(g, r)
 
 
+def test_failed_request_leaves_others_unchanged():
+    """Failure isolation: a request whose input holds a non-finite entry (the
+    fault injected here) ends with its own numeric status, and the requests
+    served beside it return exactly what they return alone."""
+    reqs = make_requests(8, 31)
+    bad = dict(reqs[3], precision="f64")
+    a_bad = bad["A"].clone()
+    a_bad[5, 7] = float("nan")
+    bad["A"] = a_bad
+    good = reqs[:3] + reqs[4:]
+    ref = alone(good)
+    torch.cuda.synchronize()
+    order = reqs[:3] + [bad] + reqs[4:]
+    with rlu.Server(hbm_budget_bytes=4 << 30, max_inflight=4) as srv:
+        tickets = [srv.submit(r["A"], k=r["k"], l=r["l"], s=r["s"], seed=r["seed"], precision=r["precision"])
+                   for r in order]
+        outs = [srv.wait(t) for t in tickets]
+    torch.cuda.synchronize()
+    assert outs[3].info_dict()["status"] == rlu.RLU_ERR_NUMERIC
+    assert outs[3].info_dict()["nonfinite"] > 0
+    for g, r in zip(outs[:3] + outs[4:], ref):
+        same(g, r)
+
+
 def test_tight_pool_queues_and_backfills():
     reqs = make_requests(10, 23)
     sizes = [rlu.workspace_size(r["A"], k=r["k"], l=r["l"], s=r["s"], precision=r["precision"]) for r in reqs]
