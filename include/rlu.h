@@ -298,7 +298,13 @@ rlu_status rlu_stage_times(rlu_ctx *ctx, float *ms, int *calls);
 
 /* Start the request loop: at most `max_inflight` requests on the device at
  * once, their workspaces carved from one pool of `hbm_budget_bytes` that the
- * library allocates here (freed by rlu_serve_stop). */
+ * library allocates here (freed by rlu_serve_stop).  Served requests launch
+ * their LU panels as ordinary launches, not cooperative ones: a request is
+ * admitted only while the panel blocks of all running requests, its own
+ * included, number at most one per compute unit, so every waiting block's
+ * siblings can be placed.  Other work on the device from outside the loop
+ * can still hold compute units; the exchange's bounded wait then ends the
+ * request with RLU_ERR_DEVICE (info.timeouts > 0) instead of hanging. */
 rlu_status rlu_serve_start(rlu_ctx *ctx, size_t hbm_budget_bytes, int max_inflight);
 
 /* Queue one decomposition; returns at once with a ticket (host out-param).
@@ -313,8 +319,8 @@ rlu_status rlu_submit(rlu_ctx *ctx, const rlu_matrix *A, const rlu_params *p,
 rlu_status rlu_poll(rlu_ctx *ctx, uint64_t ticket);
 
 /* Counters of the serving loop (host out-param, 8 words): [0] 1 when the
- * loop has one slot, whose requests run with the device to themselves (LU
- * panels as ordinary launches, each request's stages as one HIP graph),
+ * loop has one slot, whose requests run one at a time (each request's stages
+ * as one HIP graph),
  * [1] compute units the requests are planned for, [2] requests launched as
  * graphs, [3] of those, graphs updated in place, [4] graphs instantiated,
  * [5] requests enqueued directly because capture or instantiation failed,

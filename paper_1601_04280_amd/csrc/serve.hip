@@ -4,7 +4,8 @@
 // stream of default priority, an auxiliary stream and a completion event
 // each).  rlu_submit validates and plans a request and queues it.  A worker
 // thread admits queued requests whenever a slot is free and the pool has room
-// for the request's workspace (serve_policy.h: first fit, oldest first,
+// for the request's workspace and the device for its LU panel blocks
+// (serve_policy.h: first fit, oldest first,
 // younger ones may pass a head that does not fit a bounded number of times),
 // enqueues the request's whole stage sequence on the slot's stream, and
 // retires it when the slot's event completes, returning its workspace to the
@@ -14,17 +15,20 @@
 // the pool, outputs in the caller's device buffers.  rlu_poll retires
 // finished tickets.
 //
-// One slot (max_inflight = 1): requests run one at a time with the device
-// to themselves, so their LU panels, whose blocks wait for each other, are
-// ordinary launches (every block resident) instead of cooperative ones,
-// which leave the device idle for about 11 us around each panel; and each
+// LU panels, whose blocks wait for each other, are ordinary launches
+// instead of cooperative ones (which leave the device idle for about 11 us
+// around each panel): a request is admitted only while the panel blocks of
+// all running requests, its own included, number at most one per compute
+// unit, which keeps every waiting block's siblings placeable.
+//
+// One slot (max_inflight = 1): requests run one at a time, and each
 // request's stage sequence is captured into a HIP graph on the slot stream
 // and launched as one graph.  The slot keeps the instantiated graphs of
 // recent launch topologies and updates one in place (hipGraphExecUpdate) for
 // a request with the same topology.  The stages run in order on the slot
 // stream, so a graph is one chain of nodes.  With more slots, requests share
-// the device, their panels are cooperative launches, as for rlu_factor, and
-// their stages are enqueued directly.
+// the device and their stages are enqueued directly.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -90,6 +94,7 @@ struct ServeRequest {
   rlu_factors out;
   FactorPlan fp;
   size_t bytes;
+  int blocks = 0;  // blocks of the request's widest LU panel launch
   int bypassed = 0;
 };
 
@@ -101,6 +106,7 @@ struct ServeSlot {
   bool busy = false;
   uint64_t ticket = 0;
   size_t off = 0, bytes = 0;
+  int blocks = 0;
   rlu_status status = RLU_OK;
   std::string msg;
 };
@@ -139,7 +145,13 @@ static rlu_status launch_request(ServeState *s, ServeSlot &sl, const ServeReques
   ExecEnv env;
   env.caps = s->caps;
   env.ax = sl.ax;
-  env.exclusive = s->exclusive_slot;
+  // LU panels are ordinary launches, not cooperative ones: the blocks of a
+  // panel wait for each other, and admission keeps the panel blocks of all
+  // running requests within one per compute unit, so while any panel block
+  // waits for a sibling not yet placed, some compute unit holds no waiting
+  // block and frees up as its other work ends.  (The waits are also bounded
+  // in time and end in RLU_ERR_TIMEOUT.)
+  env.exclusive = true;
   env.overlap = !s->exclusive_slot;
   if (!s->exclusive_slot) return factor_enqueue(*s->cx, &r.A, &r.p, &r.out, ws, r.fp, sl.st, &env);
   ++s->launches;
@@ -232,7 +244,11 @@ static void worker_main(ServeState *s) {
     for (ServeSlot &sl : s->slots) {  // admit into free slots
       if (sl.busy) continue;
       size_t off = 0;
-      const int idx = serve::pick_next(s->queue, s->alloc, kMaxBypass, &off);
+      // LU panel blocks of the running requests: together at most one per
+      // compute unit (see launch_request)
+      int held = 0;
+      for (const ServeSlot &o : s->slots) held += o.busy ? o.blocks : 0;
+      const int idx = serve::pick_next(s->queue, s->alloc, s->caps.num_cu - held, kMaxBypass, &off);
       if (idx < 0) break;
       ServeRequest r = s->queue[idx];
       s->queue.erase(s->queue.begin() + idx);
@@ -240,6 +256,7 @@ static void worker_main(ServeState *s) {
       sl.ticket = r.ticket;
       sl.off = off;
       sl.bytes = r.bytes;
+      sl.blocks = r.blocks;
       ++s->running;
       s->tickets[r.ticket].state = kRunning;
       lk.unlock();  // launching does not hold up rlu_submit / rlu_poll
@@ -382,6 +399,7 @@ rlu_status rlu_submit(rlu_ctx *ctx, const rlu_matrix *A, const rlu_params *p, co
   r.p = *p;
   r.out = *out;
   r.bytes = r.fp.total;
+  r.blocks = std::max(r.fp.py.G, r.fp.pb.G);
   {
     std::lock_guard<std::mutex> g(s->mu);
     if (s->stopping) return fail(RLU_ERR_INVALID_ARG, "serving is stopping");

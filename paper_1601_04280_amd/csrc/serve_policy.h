@@ -78,18 +78,21 @@ class PoolAlloc {
   std::map<size_t, size_t> free_;
 };
 
-// Admission: the oldest queued request if its workspace fits.  If it does not,
-// a younger one that fits may go first (so small requests keep the device
-// busy while memory for a large one frees up), but at most `max_bypass`
-// times for the same head, after which the loop waits for the head.
-// Returns the queue index to admit and its offset, or -1.
+// Admission: the oldest queued request if its workspace fits the pool and
+// its LU panel blocks fit `blocks_free` (what the running requests leave of
+// the compute units).  If it does not, a younger one that fits may go first
+// (so small requests keep the device busy while memory or blocks for a large
+// one free up), but at most `max_bypass` times for the same head, after
+// which the loop waits for the head.  Returns the queue index to admit and
+// its offset, or -1.
 template <typename Req>
-int pick_next(std::deque<Req> &queue, PoolAlloc &pool, int max_bypass, size_t *off) {
+int pick_next(std::deque<Req> &queue, PoolAlloc &pool, int blocks_free, int max_bypass, size_t *off) {
   if (queue.empty()) return -1;
-  if (pool.alloc(queue.front().bytes, off)) return 0;
+  auto fits = [&](const Req &r) { return r.blocks <= blocks_free && pool.alloc(r.bytes, off); };
+  if (fits(queue.front())) return 0;
   if (queue.front().bypassed >= max_bypass) return -1;
   for (size_t i = 1; i < queue.size(); ++i) {
-    if (pool.alloc(queue[i].bytes, off)) {
+    if (fits(queue[i])) {
       ++queue.front().bypassed;
       return (int)i;
     }

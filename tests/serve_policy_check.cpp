@@ -21,6 +21,7 @@ using rlu::serve::kGranule;
 
 struct Req {
   size_t bytes;
+  int blocks = 1;
   int bypassed = 0;
 };
 
@@ -94,25 +95,45 @@ static int admission() {
   q.push_back({2 * kGranule});
   q.push_back({1 * kGranule});
   size_t off;
-  int idx = rlu::serve::pick_next(q, p, 2, &off);
+  int idx = rlu::serve::pick_next(q, p, 4, 2, &off);
   CHECK(idx == 1 && q.front().bypassed == 1);  // younger request passes the head
   q.erase(q.begin() + idx);
-  idx = rlu::serve::pick_next(q, p, 2, &off);
+  idx = rlu::serve::pick_next(q, p, 4, 2, &off);
   CHECK(idx == 1 && q.front().bypassed == 2);
   q.erase(q.begin() + idx);
   q.push_back({1});
-  idx = rlu::serve::pick_next(q, p, 2, &off);
+  idx = rlu::serve::pick_next(q, p, 4, 2, &off);
   CHECK(idx == -1);                              // bypass budget spent: wait for the head
   p.release(hold, 5 * kGranule);
-  idx = rlu::serve::pick_next(q, p, 2, &off);
+  idx = rlu::serve::pick_next(q, p, 4, 2, &off);
   CHECK(idx == 0);                               // the head goes once memory frees up
   std::deque<Req> empty;
-  CHECK(rlu::serve::pick_next(empty, p, 2, &off) == -1);
+  CHECK(rlu::serve::pick_next(empty, p, 4, 2, &off) == -1);
+  return 0;
+}
+
+// The second resource: a request whose panel blocks exceed what the running
+// requests leave waits like one whose workspace does not fit, and takes no
+// pool memory while it waits.
+static int admission_blocks() {
+  PoolAlloc p(8 * kGranule);
+  std::deque<Req> q;
+  q.push_back({2 * kGranule, 6});   // needs more blocks than are free
+  q.push_back({2 * kGranule, 3});
+  q.push_back({2 * kGranule, 5});
+  size_t off;
+  int idx = rlu::serve::pick_next(q, p, 4, 1, &off);
+  CHECK(idx == 1 && q.front().bypassed == 1 && p.used() == 2 * kGranule);
+  q.erase(q.begin() + idx);
+  idx = rlu::serve::pick_next(q, p, 1, 1, &off);
+  CHECK(idx == -1 && p.used() == 2 * kGranule);  // bypass spent, and the head still lacks blocks
+  idx = rlu::serve::pick_next(q, p, 6, 1, &off);
+  CHECK(idx == 0 && p.used() == 4 * kGranule);   // blocks freed: the head goes
   return 0;
 }
 
 int main() {
-  if (basic() || fuzz() || admission()) return 1;
+  if (basic() || fuzz() || admission() || admission_blocks()) return 1;
   std::printf("ok\n");
   return 0;
 }
