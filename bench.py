@@ -28,8 +28,9 @@ Unless --no-extras (or a shorter --extras list), the line also carries
            log-uniform in [512, 8192], n in [256, 4096], k in {16 .. 256},
            l = k + 10, s = min(n, 8k), 30% BF16-refined, dense
            low-rank-plus-noise (sigma_i = 2^-(i-1), r = 20, noise 1e-10);
-           Poisson arrivals at 0.5, 0.7 and 0.9 of the measured saturated
-           rate, p50 / p99 latency (completion - arrival) and decomps/s;
+           Poisson arrivals at 0.05 (latency close to the service time
+           alone), 0.5, 0.7 and 0.9 of the measured saturated rate, p50 /
+           p99 latency (completion - arrival) and decomps/s;
   `accuracy`: the experiments of Section 4.1 (sigma_1..r = 1, then e^-10 down
            to e^-200) and 4.2 (sigma from 1 down to e^-100) on 5000 x 5000
            matrices: ||LU - PAQ||_F against Delta_r and the time, per rank r.
@@ -454,7 +455,7 @@ def csr_block(rlu, ctx, dev):
     return res
 
 
-def serve_block(rlu, dev, counts=(600, 2000, 600), fracs=(0.5, 0.7, 0.9), n_sat=400, max_inflight=8):
+def serve_block(rlu, dev, counts=(300, 600, 2000, 600), fracs=(0.05, 0.5, 0.7, 0.9), n_sat=2000, max_inflight=8):
     import numpy as np
     import torch
     import synth
