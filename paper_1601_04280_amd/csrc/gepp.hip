@@ -125,27 +125,6 @@ __device__ inline void put_header_word(uint64_t *hp, int64_t hs, const Cand &c, 
   tw_put(hp + w * hs, d, tag);
 }
 
-// Block-wide copy of `total` values into LDS: load(e) -> dst(e), with eight
-// global loads in flight per thread before any LDS store (a plain strided
-// loop would wait for every load in turn).
-template <typename LoadF, typename StoreF>
-__device__ inline void block_copy(int total, LoadF load, StoreF store) {
-  constexpr int B = 8;
-  for (int e0 = threadIdx.x; e0 < total; e0 += kGeppThreads * B) {
-    double v[B];
-#pragma unroll
-    for (int u = 0; u < B; ++u) {
-      const int e = e0 + kGeppThreads * u;
-      v[u] = (e < total) ? load(e) : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < B; ++u) {
-      const int e = e0 + kGeppThreads * u;
-      if (e < total) store(e, v[u]);
-    }
-  }
-}
-
 template <int RPT, int NB>
 __global__ __launch_bounds__(kGeppThreads) void k_gepp_panel(GeppKArgs a) {
   constexpr int NW = kGeppThreads / 64;
@@ -498,17 +477,26 @@ __global__ __launch_bounds__(256) void k_u12_mfma(int l, int j0, int nbp, const 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int j1 = j0 + nbp, cb = j1 + blockIdx.x * NB;
-  block_copy(NB * NB, [&](int e) {
-    const int t = e / NB, u = e % NB;
-    return (t < nbp && u < t) ? Lhat[(int64_t)rowAt[j0 + t] * l + j0 + u] : 0.0;
-  }, [&](int e, double v) {
-    const int t = e / NB, u = e % NB;
-    Ls[t * P + u] = (t == u) ? 1.0 : v;
-  });
-  block_copy(NB * NB, [&](int e) {
-    const int i = e / NB, c = e % NB;
-    return (i < nbp && cb + c < l) ? X[(int64_t)rowAt[j0 + i] * ldx + cb + c] : 0.0;
-  }, [&](int e, double v) { Xs[(e / NB) * P + e % NB] = v; });
+  // Tile row t = wave + 4 u, column = lane: the row is uniform in the wave,
+  // so its pivot row comes from the one rowAt load per lane by readlane and
+  // all 32 tile loads of a thread are in flight together (unconditional,
+  // from clamped in-range addresses, the out-of-range values zeroed after).
+  const int prow = lane < nbp ? rowAt[j0 + lane] : 0;
+  const int lc = min(j0 + lane, l - 1), xc = min(cb + lane, l - 1);
+  double lv[16], xv[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u)
+    lv[u] = Lhat[(int64_t)__builtin_amdgcn_readlane(prow, wave + 4 * u) * l + lc];
+#pragma unroll
+  for (int u = 0; u < 16; ++u)
+    xv[u] = X[(int64_t)__builtin_amdgcn_readlane(prow, wave + 4 * u) * ldx + xc];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int t = wave + 4 * u;
+    Ls[t * P + lane] = (t < nbp && lane < t) ? lv[u] : 0.0;
+  }
+  // the unit diagonal, by the lane that zeroed it (row lane is this wave's)
+  if ((lane & 3) == wave) Ls[lane * P + lane] = 1.0;
   __syncthreads();
   if (tid < 64) {  // column c of D_I, I = tid / 16
     const int I = tid >> 4, c = tid & 15;
@@ -521,6 +509,12 @@ __global__ __launch_bounds__(256) void k_u12_mfma(int l, int j0, int nbp, const 
       x[r] = sum;
       Ds[I][r][c] = sum;
     }
+  }
+  // X's loads were in flight during the inversions
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int t = wave + 4 * u;
+    Xs[t * P + lane] = (t < nbp && cb + lane < l) ? xv[u] : 0.0;
   }
   __syncthreads();
   const int lr = lane & 15, lk = lane >> 4;
