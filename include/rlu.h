@@ -142,7 +142,9 @@ typedef struct {
                                * side of every panel (8 panels at l = 210).  If other work does
                                * keep some blocks from starting, the exchange gives up after
                                * 2 s and the call reports RLU_ERR_DEVICE with info.timeouts > 0;
-                               * it does not hang.  Not accepted for served requests. */
+                               * it does not hang.  Not accepted for served requests: the
+                               * serving loop launches their panels this way by itself, under
+                               * its admission rule (rlu_serve_start). */
 #define RLU_FLAG_HADAMARD 16u  /* the sketch's transform T is the Walsh-Hadamard matrix
                                 * H_s / sqrt(s) in Sylvester order, H[b][c] = (-1)^popcount(b & c)
                                 * (the subsampled randomized Hadamard transform of Section 4),
