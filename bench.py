@@ -510,7 +510,7 @@ def serve_block(rlu, dev, counts=(300, 600, 2000, 600), fracs=(0.05, 0.5, 0.7, 0
                             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
                             "mean_ms": round(float(lat.mean()) * 1e3, 3),
                             "decomps_per_s": round(count / wall, 2)})
-        print(f"# serving {frac:.1f} x saturated ({rate:.0f}/s): p50 {res['runs'][-1]['p50_ms']} ms, "
+        print(f"# serving {frac:.2f} x saturated ({rate:.0f}/s): p50 {res['runs'][-1]['p50_ms']} ms, "
               f"p99 {res['runs'][-1]['p99_ms']} ms", file=sys.stderr, flush=True)
     res["loop"] = srv.stats()
     srv.stop()
