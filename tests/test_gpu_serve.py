@@ -112,6 +112,27 @@ def test_tight_pool_queues_and_backfills():
         same(g, r)
 
 
+def test_wide_requests_wait_for_panel_blocks():
+    """Admission by panel blocks: a 65536-row request's LU panels take one
+    block per compute unit, so two of them never run together, while small
+    requests may pass a wide one that is waiting; every result is still the
+    one the request gets alone."""
+    wide = []
+    for i in range(2):
+        A = synth.lowrank_dense(65536, 512, 1.0 / np.arange(1, 79), 4200 + i)
+        wide.append(dict(A=to_dev(A), k=16, l=26, s=256, seed=70 + i, precision="f64"))
+    small = make_requests(4, 47)
+    reqs = [wide[0], small[0], wide[1], small[1], small[2], small[3]]
+    ref = alone(reqs)
+    torch.cuda.synchronize()
+    with rlu.Server(hbm_budget_bytes=4 << 30, max_inflight=4) as srv:
+        tickets = [srv.submit(r["A"], k=r["k"], l=r["l"], s=r["s"], seed=r["seed"], precision=r["precision"])
+                   for r in reqs]
+        outs = [srv.wait(t) for t in tickets]
+    for g, r in zip(outs, ref):
+        same(g, r)
+
+
 def test_serving_errors():
     A = to_dev(np.random.default_rng(0).standard_normal((500, 400)))
     big = to_dev(np.random.default_rng(1).standard_normal((3000, 2000)))
