@@ -586,7 +586,7 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     GemmArgs g{};
     g.M = m; g.N = l; g.K = l;
     g.A = Lhat; g.lda = l; g.a_dtype = RLU_F64; g.trans_a = false; g.gather = out->perm_r;
-    g.B = Lt; g.ldb = l;
+    g.B = Lt; g.ldb = l; g.b_lower = true;  // L~ is unit lower triangular
     g.C = out->L; g.ldc = out->ldl; g.alpha = 1.0; g.beta = 0.0;
     if ((e = gemm_f64(g, st)) != hipSuccess) return hip_fail(e, "L = L_y L~");
   }

@@ -61,6 +61,7 @@ struct GemmK {
   int64_t Kc;       // K extent of one split
   double alpha, beta;
   int partial;
+  int b_lower;  // B lower triangular: K starts at the column tile's first column
 };
 
 constexpr int kBK = 16;
@@ -83,8 +84,11 @@ __global__ __launch_bounds__(128 * WGM, 1) void k_gemm(GemmK p) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
   const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
-  const int64_t kb = (int64_t)blockIdx.z * p.Kc;
-  const int64_t ke = min(p.K, kb + p.Kc);
+  const int64_t ks = (int64_t)blockIdx.z * p.Kc;
+  const int64_t ke = min(p.K, ks + p.Kc);
+  // rows k < n0 of a lower-triangular B are zero in this tile's columns (n0
+  // is a multiple of kBK, so the stages stay aligned)
+  const int64_t kb = p.b_lower ? max(ks, n0) : ks;
   const TAt *A = reinterpret_cast<const TAt *>(p.A);
   const TC *B = reinterpret_cast<const TC *>(p.B);
 
@@ -463,8 +467,10 @@ static hipError_t launch(const GemmArgs &g, int splits, int64_t Kc, double *part
   if (g.trans_b) return hipErrorInvalidValue;
   Shape sh = pick_shape(g.M, g.N, g.K);
   if (wide) sh.wgm = 4;
+  if (g.b_lower) sh.fn = std::min(sh.fn, 2);  // 64-column tiles: each skips its zero rows of B
   GemmK k;
   k.M = g.M; k.N = g.N; k.K = g.K;
+  k.b_lower = g.b_lower ? 1 : 0;
   k.A = g.A; k.lda = g.lda; k.gather = g.gather;
   k.B = g.B; k.ldb = g.ldb;
   k.alpha = g.alpha; k.beta = g.beta;
@@ -482,7 +488,7 @@ static hipError_t launch(const GemmArgs &g, int splits, int64_t Kc, double *part
     const bool full = sh.wgm == 4 && sh.fm == 2 && g.M % 128 == 0 && g.K % kBK == 0 && Kc % kBK == 0 &&
                       g.N % 4 == 0 && g.lda % (f32a ? 4 : 2) == 0 && g.ldb % 4 == 0 &&
                       ((reinterpret_cast<uintptr_t>(g.A) | reinterpret_cast<uintptr_t>(g.B)) & 15) == 0 &&
-                      (k.partial || g.beta == 0.0);
+                      (k.partial || g.beta == 0.0) && !g.b_lower;
     if (full) {
       switch (sh.fn) {
 #define RLU_FN(F)                                                                            \
@@ -505,7 +511,7 @@ static hipError_t launch(const GemmArgs &g, int splits, int64_t Kc, double *part
     const bool full = sh.wgm == 4 && sh.fm == 2 && g.M % 128 == 0 && g.K % kBK == 0 && Kc % kBK == 0 &&
                       g.N % 2 == 0 && g.lda % (f32a ? 4 : 2) == 0 && g.ldb % 2 == 0 &&
                       ((reinterpret_cast<uintptr_t>(g.A) | reinterpret_cast<uintptr_t>(g.B)) & 15) == 0 &&
-                      (k.partial || g.beta == 0.0);
+                      (k.partial || g.beta == 0.0) && !g.b_lower;
     if (full) {
       switch (sh.fn) {
 #define RLU_FN(F)                                                                     \

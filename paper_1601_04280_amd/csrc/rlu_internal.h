@@ -146,6 +146,10 @@ struct GemmArgs {
   double *C; int64_t ldc;
   double alpha, beta;
   int compute;
+  // B is lower triangular (B[k][j] = 0 for k < j): a column tile starting
+  // at n0 sums from k = n0 only, and the tiles are narrow so that few of
+  // their K steps are spent on B's zero part
+  bool b_lower;
 };
 // Plain (no split): writes C directly.
 hipError_t gemm_f64(const GemmArgs &g, hipStream_t st);
