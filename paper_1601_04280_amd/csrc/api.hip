@@ -492,7 +492,7 @@ rlu_status factor_enqueue(rlu_ctx_impl &cx, const rlu_matrix *A, const rlu_param
     GemmArgs g{};
     g.M = l; g.N = l; g.K = l;
     g.A = at<double>(ws, fp.Linv); g.lda = l; g.a_dtype = RLU_F64; g.trans_a = true;
-    g.B = at<double>(ws, fp.Linv); g.ldb = l;
+    g.B = at<double>(ws, fp.Linv); g.ldb = l; g.b_lower = true;  // Linv is lower triangular
     g.C = at<double>(ws, fp.Ginv); g.ldc = l; g.alpha = 1.0; g.beta = 0.0;
     if ((e = gemm_f64_splitk(g, fp.splits_i, at<double>(ws, fp.parts_g), gs)) != hipSuccess)
       return hip_fail(e, "inverse Gram");
