@@ -95,3 +95,13 @@ def test_oversampling_is_kept():
 
 def _f(o):
     return o.L, o.U, o.perm_r, o.perm_c
+
+
+def test_truncated_pipeline_factors_the_chosen_columns_in_pivot_order():
+    """Steps 3-7 run on Y_k = the chosen columns of Y in the order column
+    pivoting chose them: P Y_k = L_y U_y holds for that order."""
+    A = synth.lowrank_dense(400, 300, 0.8 ** np.arange(80), 6, noise=1e-6)
+    o = R.rlu(A, R.Params(12, 40, 64, 2, truncate=True))
+    assert np.any(np.diff(o.ysel) < 0), "selection happens to be sorted: order not exercised"
+    Yk = o.Y[:, o.ysel]
+    np.testing.assert_allclose(o.Ly @ o.Uy, Yk[o.perm_r], rtol=0, atol=1e-12 * np.abs(Yk).max())

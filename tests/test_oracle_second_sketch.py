@@ -117,3 +117,15 @@ def test_second_projection_csr_and_dense_agree():
     np.testing.assert_array_equal(d.perm_r, s.perm_r)
     np.testing.assert_array_equal(d.perm_c, s.perm_c)
     np.testing.assert_allclose(s.B, d.B, rtol=1e-10, atol=1e-12)
+
+
+def test_pipeline_draws_omega2_independently_of_omega1():
+    """Algorithm 1 step 4 draws Omega_2 afresh: at equal sizes (m = n,
+    l2 = s) the pipeline's Omega_2 parameters must not repeat Omega_1's."""
+    p = R.Params(8, 16, 256, 5, k2=64, l2=256)
+    h, sgn, d, sel = R.sketch_params(2000, p)
+    h2, sgn2, d2, sel2 = R.omega2_params(2000, p)
+    assert np.mean(h == h2) < 0.02                 # about 1/256 by chance
+    assert np.mean(sgn == sgn2) < 0.6              # about 1/2 by chance
+    assert np.mean(d == d2) < 0.65
+    assert len(set(sel[:16]) & set(sel2[:16])) < 8
