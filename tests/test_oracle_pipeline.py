@@ -73,6 +73,11 @@ def test_tail_norm_hand_values():
     want = {0: np.sqrt(55.0), 1: np.sqrt(30.0), 2: np.sqrt(14.0), 3: np.sqrt(5.0), 4: 1.0, 5: 0.0}
     for k, v in want.items():
         assert R.tail_norm(A, k) == pytest.approx(v, rel=1e-14, abs=1e-14), k
+    # without the empty column every singular value is nonzero (the last
+    # one, 1, is in every tail but the empty one)
+    A5 = np.delete(A, 3, axis=1)
+    for k, v in want.items():
+        assert R.tail_norm(A5, k) == pytest.approx(v, rel=1e-14, abs=1e-14), k
 
 
 def test_rank_exact_input_is_reproduced():

@@ -66,6 +66,18 @@ def test_streams_differ_and_seeds_differ():
     assert np.mean(h1 == h2) < 0.05
 
 
+@pytest.mark.parametrize("seed", [0, 3, 2**64 - 7])
+def test_streams_are_the_published_generator(seed):
+    """The stream key K_t is the t-th output of SplitMix64 started at the
+    seed, and draw i of stream t is output i + 1 of SplitMix64 started at K_t:
+    both through the sequence that the published known answers pin."""
+    seq = rng.splitmix64_sequence(seed, 6)
+    for t in range(1, 7):
+        key = rng.stream_key(seed, t)
+        assert key == seq[t - 1]
+        assert [rng.draw(key, i) for i in range(40)] == rng.splitmix64_sequence(key, 40)
+
+
 @pytest.mark.parametrize("bad", [0, 1, 3, 12])
 def test_bad_width_rejected(bad):
     with pytest.raises(ValueError):
