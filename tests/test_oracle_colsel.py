@@ -105,3 +105,14 @@ def test_truncated_pipeline_factors_the_chosen_columns_in_pivot_order():
     assert np.any(np.diff(o.ysel) < 0), "selection happens to be sorted: order not exercised"
     Yk = o.Y[:, o.ysel]
     np.testing.assert_allclose(o.Ly @ o.Uy, Yk[o.perm_r], rtol=0, atol=1e-12 * np.abs(Yk).max())
+
+
+def test_selection_gap_hand_value():
+    """Orthogonal columns of norms 2, 4, 3: the candidates' d are 16, 9, 4
+    at step 0 (gap 7/16) and 9, 4 at step 1 (gap 5/9); the screening gap is
+    the smaller, relative to the top candidate."""
+    Y = np.zeros((5, 3))
+    Y[0, 0], Y[1, 1], Y[2, 2] = 2.0, 4.0, 3.0
+    sel, rdiag, zero, gap = colsel.pivoted_cholesky_order(Y, 2)
+    assert sel.tolist() == [1, 2]
+    assert gap == pytest.approx(7.0 / 16.0, abs=1e-15)

@@ -112,3 +112,17 @@ def test_nonfinite_raises():
         lu.gepp(y)
     with pytest.raises(FloatingPointError):
         lu.colpiv_lu(y.T.copy())
+
+
+def test_pivot_gap_hand_values():
+    """The screening gap is the smallest (top - second) / top over the
+    steps.  Y: step 0 sees |4|, |3|, 0 (gap 1/4), step 1 sees 2, 1 (gap 1/2).
+    B: step 0 sees |4|, |3|, 0 in row 0 (1/4); row 1 is untouched by the
+    elimination (multiplier 0) and step 1 sees 2, 1 (1/2)."""
+    Y = np.array([[4.0, 0.0], [3.0, 2.0], [0.0, 1.0]])
+    assert lu.gepp(Y)[5] == pytest.approx(0.25, abs=1e-15)
+    B = np.array([[4.0, 3.0, 0.0], [0.0, 2.0, 1.0]])
+    assert lu.colpiv_lu(B)[5] == pytest.approx(0.25, abs=1e-15)
+    # the step-1 gap alone, when step 0's is wider
+    assert lu.gepp(np.array([[4.0, 0.0], [1.0, 2.0], [0.0, 1.0]]))[5] == pytest.approx(0.5, abs=1e-15)
+    assert lu.colpiv_lu(np.array([[4.0, 1.0, 0.0], [0.0, 2.0, 1.0]]))[5] == pytest.approx(0.5, abs=1e-15)

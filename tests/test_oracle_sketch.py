@@ -175,3 +175,18 @@ def test_hadamard_sketch_brute_force(m, n, s, l):
     csr = sp.csr_matrix(a)
     yc = sketch.sketch_csr(csr.indptr, csr.indices, csr.data, m, n, h, sgn, d, sel, s, "hadamard")
     np.testing.assert_allclose(yc, a @ omega_t, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("transform", ["fourier", "hadamard"])
+def test_csr_sketch_spans_row_chunks(transform):
+    """The CSR sketch of a matrix with more rows than one processing chunk
+    (5000) equals the sketch of the same matrix held dense."""
+    rs = np.random.default_rng(12)
+    a = sp.random(5000, 300, density=0.02, format="csr", random_state=rs,
+                  data_rvs=lambda k: rs.standard_normal(k))
+    h, sgn = rng.sem_hash(4, 300, 64)
+    d = rng.srft_signs(4, 64)
+    sel = rng.srft_select(4, 64, 20)
+    got = sketch.sketch_csr(a.indptr, a.indices, a.data, 5000, 300, h, sgn, d, sel, 64, transform)
+    want = sketch.sketch_dense(a.toarray(), h, sgn, d, sel, 64, transform)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
