@@ -94,16 +94,18 @@ static int admission() {
   q.push_back({4 * kGranule});          // head does not fit
   q.push_back({2 * kGranule});
   q.push_back({1 * kGranule});
-  size_t off;
+  size_t off, off2;
   int idx = rlu::serve::pick_next(q, p, 4, 2, &off);
   CHECK(idx == 1 && q.front().bypassed == 1);  // younger request passes the head
   q.erase(q.begin() + idx);
-  idx = rlu::serve::pick_next(q, p, 4, 2, &off);
+  idx = rlu::serve::pick_next(q, p, 4, 2, &off2);
   CHECK(idx == 1 && q.front().bypassed == 2);
   q.erase(q.begin() + idx);
+  p.release(off2, 1 * kGranule);                 // memory for a third younger one is there
   q.push_back({1});
+  const size_t used = p.used();
   idx = rlu::serve::pick_next(q, p, 4, 2, &off);
-  CHECK(idx == -1);                              // bypass budget spent: wait for the head
+  CHECK(idx == -1 && p.used() == used);          // bypass budget spent: wait for the head
   p.release(hold, 5 * kGranule);
   idx = rlu::serve::pick_next(q, p, 4, 2, &off);
   CHECK(idx == 0);                               // the head goes once memory frees up
