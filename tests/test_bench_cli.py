@@ -30,3 +30,21 @@ def test_sweep_parameters(r, l, s):
 def test_headline_workload_is_the_dense_invsq_matrix():
     w = bench.WORKLOADS["dense_16384x8192_invsq"]
     assert (w["m"], w["n"], w["k"], w["l"], w["s"], w["precision"]) == (16384, 8192, 200, 210, 2048, "f64")
+
+
+def test_measured_traffic_only_for_the_source_it_was_taken_on(tmp_path, monkeypatch):
+    """The roofline's traffic comes from the committed counter summary only
+    while the kernel source hashes as it did when the counters were taken."""
+    import hashlib
+    import json
+    (tmp_path / "profiles").mkdir()
+    src = tmp_path / "k.hip"
+    src.write_text("kernel v1\n")
+    rec = {"kern": {"kernel": "k", "source": "k.hip", "bytes_per_launch": 1234,
+                    "source_sha256": hashlib.sha256(b"kernel v1\n").hexdigest()}}
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "HERE", str(tmp_path))
+    assert bench.measured_traffic("kern") == 1234
+    assert bench.measured_traffic("other") is None
+    src.write_text("kernel v2\n")
+    assert bench.measured_traffic("kern") is None
